@@ -1,0 +1,169 @@
+/*
+ * xsum: exact summation of IEEE binary floating-point numbers on AMD
+ * Instinct MI355X (gfx950), returning the sum rounded once.
+ *
+ * Method (Goodrich & Eldawy, "Parallel Algorithms for Summing
+ * Floating-Point Numbers"): every input is converted to an exact integer
+ * representation, the integers are summed without rounding, and the exact
+ * total is rounded to a float at the end (Section 1, the problem statement,
+ * asks for a faithful rounding of the exact sum).  This library returns the
+ * round-to-nearest, ties-to-even result, which is one of the two faithful
+ * answers and is unique, so results are bit-reproducible regardless of launch
+ * shape, order or batching.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked "device" must be device memory of the current HIP device
+ *    (hipMalloc, or any allocator returning such memory, e.g. PyTorch).  The
+ *    caller owns every buffer and every stream it passes; the library keeps no
+ *    reference to them after a call returns (asynchronous calls: after the
+ *    work completes on the stream).
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *  - Input elements must be aligned to their size (8, 4 or 2 bytes); 16-byte
+ *    alignment gives the fastest path.  Any length is accepted, including 0.
+ *  - Errors are returned as status codes; no exception crosses the interface.
+ *    xsum_last_error() returns a thread-local message for the last failing
+ *    call on the calling thread.
+ *  - Infinities and NaNs are not errors.  The paper assumes finite inputs;
+ *    this library follows IEEE addition for them: a NaN input, or both +inf
+ *    and -inf, gives the canonical quiet NaN; otherwise an infinite input
+ *    gives that infinity.
+ *  - An exact sum of zero is returned as +0.0.  A non-zero exact sum that
+ *    rounds beyond the largest finite value returns an infinity of its sign
+ *    with XSUM_FLAG_OVERFLOW.
+ *  - Calls on distinct streams with distinct workspaces may overlap.
+ */
+#ifndef XSUM_H
+#define XSUM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element formats (IEEE 754 binary64, binary32; bfloat16 = upper half of a
+ * binary32).  XSUM_SAME as an output format means: binary64 for binary64
+ * input, binary32 for binary32 and bfloat16 input. */
+typedef enum {
+    XSUM_F64 = 0,
+    XSUM_F32 = 1,
+    XSUM_BF16 = 2,
+    XSUM_SAME = 255
+} xsum_dtype_t;
+
+typedef enum {
+    XSUM_OK = 0,
+    XSUM_EINVAL = 1,  /* null pointer, misaligned input, bad size */
+    XSUM_EDTYPE = 2,  /* unknown input or output format */
+    XSUM_ENOMEM = 3,  /* library-owned allocation failed */
+    XSUM_EHIP = 4,    /* a HIP runtime call failed (message has the code) */
+    XSUM_ERANGE = 5   /* a size exceeds a documented limit */
+} xsum_status_t;
+
+/* Result flags (bitwise OR). */
+#define XSUM_FLAG_INEXACT 1u   /* the finite result differs from the exact sum */
+#define XSUM_FLAG_OVERFLOW 2u  /* the exact finite sum rounded to +-infinity */
+#define XSUM_FLAG_NAN 4u       /* the result is NaN */
+#define XSUM_FLAG_INF 8u       /* some input was an infinity */
+
+/* Number of radix-2^32 digits of the exact accumulator.  Digit j weighs
+ * 2^(32 j - 1074); digit XSUM_DIGITS-1 is signed and holds the sign. */
+#define XSUM_DIGITS 68
+
+/*
+ * Exact, mergeable sum state in device memory (Section 2: a superaccumulator
+ * of integer digits whose additions need no carry propagation).  576 bytes.
+ * `digit` holds the exact sum of everything added so far; `special` records
+ * NaN (bit 0), +inf (bit 1) and -inf (bit 2) inputs; `ticket` is used by the
+ * library's kernels and must be 0 between calls.  After any xsum call that
+ * completes on a state, its digits are in canonical form (digits 0..66 in
+ * [0, 2^32), digit 67 in {-1, 0}).  A state is zeroed by xsum_acc_zero, or by
+ * a byte-wise zero fill.
+ */
+typedef struct xsum_acc {
+    int64_t digit[XSUM_DIGITS];
+    uint32_t special;
+    uint32_t ticket;
+    uint64_t reserved[3];
+} xsum_acc_t;
+
+/* Library version string (static storage). */
+const char *xsum_version(void);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *xsum_last_error(void);
+
+/*
+ * Exact sum of n elements, blocking.
+ * Section 3 (steps 2, 5, 6, 7) and Section 5 (scan algorithm when the
+ * accumulator fits in fast memory): convert each input to integer digits,
+ * add them carry-free, propagate the signed carries once, round once.
+ *   x         device, n elements of `dtype`, element-aligned (NULL iff n == 0)
+ *   out_dtype XSUM_F64, XSUM_F32, XSUM_BF16 or XSUM_SAME
+ *   out_host  host memory receiving the result bit pattern (8, 4 or 2 bytes)
+ *   flags_host host, may be NULL; receives XSUM_FLAG_* bits
+ * The library keeps one workspace per (device, stream) for this call; it is
+ * allocated on first use and kept until process exit.  Returns after the
+ * result has been copied to the host.
+ */
+xsum_status_t xsum_exact_sum(const void *x, uint64_t n, int dtype,
+                             int out_dtype, void *out_host,
+                             uint32_t *flags_host, void *stream);
+
+/* Convenience: binary64 result of xsum_exact_sum (NaN and a thread-local
+ * error message on failure). */
+double xsum_exact_sum_f64(const void *x, uint64_t n, int dtype);
+
+/*
+ * Exact sum, asynchronous, all in device memory (one kernel launch).
+ *   x, n, dtype, out_dtype as for xsum_exact_sum
+ *   out_dev   device, receives the result bit pattern (8, 4 or 2 bytes)
+ *   flags_dev device, may be NULL; receives XSUM_FLAG_* bits
+ *   scratch   device, an xsum_acc_t that is zero (xsum_acc_zero) before the
+ *             call; the call leaves it zero again.  Calls sharing a scratch
+ *             state must be ordered (same stream, or synchronised).
+ * Returns after enqueueing; results are valid when the stream reaches them.
+ */
+xsum_status_t xsum_exact_sum_async(const void *x, uint64_t n, int dtype,
+                                   int out_dtype, void *out_dev,
+                                   uint32_t *flags_dev, xsum_acc_t *scratch,
+                                   void *stream);
+
+/*
+ * xsum_exact_sum_async with an explicit grid size (number of workgroups of
+ * the accumulation kernel; 0 = the library's persistent default).  The result
+ * does not depend on `blocks`; this exists for tuning and for tests that
+ * check exactly that.  blocks < 0 is XSUM_EINVAL.
+ */
+xsum_status_t xsum_exact_sum_async_blocks(const void *x, uint64_t n,
+                                          int dtype, int out_dtype,
+                                          void *out_dev, uint32_t *flags_dev,
+                                          xsum_acc_t *scratch, int blocks,
+                                          void *stream);
+
+/*
+ * Accumulator interface (Section 2: two exact states are merged by adding
+ * digits; Section 6: reducers' states are combined by a final post-process
+ * and rounded once).  All pointers are device pointers; all calls are
+ * asynchronous on `stream`.
+ */
+/* Zero `count` consecutive states. */
+xsum_status_t xsum_acc_zero(xsum_acc_t *acc, uint64_t count, void *stream);
+/* acc += exact sum of x[0..n).  Leaves acc canonical. */
+xsum_status_t xsum_acc_add(xsum_acc_t *acc, const void *x, uint64_t n,
+                           int dtype, void *stream);
+/* dst += src (exact).  src is unchanged.  Leaves dst canonical. */
+xsum_status_t xsum_acc_merge(xsum_acc_t *dst, const xsum_acc_t *src,
+                             void *stream);
+/* Round the state once to out_dtype (XSUM_SAME means binary64).  acc is
+ * unchanged.  out_dev receives 8, 4 or 2 bytes; flags_dev may be NULL. */
+xsum_status_t xsum_acc_finalize(const xsum_acc_t *acc, int out_dtype,
+                                void *out_dev, uint32_t *flags_dev,
+                                void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XSUM_H */

@@ -1,0 +1,177 @@
+"""Python binding of libxsum: exact floating-point summation on MI355X.
+
+Argument marshalling only: every step of a sum runs in the HIP library
+(libxsum.so, built from csrc/ by ``build.py``).  If the library is missing the
+import of this module fails; there is no fallback.
+
+The C names are kept: ``xsum_exact_sum``, ``xsum_exact_sum_async``,
+``xsum_exact_sum_async_blocks``, ``xsum_acc_zero``, ``xsum_acc_add``,
+``xsum_acc_merge``, ``xsum_acc_finalize``, ``xsum_last_error``.  They take raw
+device pointers (ints) and a stream handle (int, 0 = default stream).  The
+helpers ``exact_sum``, ``new_states`` and ``stream_handle`` accept PyTorch
+tensors, which serve only as device memory and streams.
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxsum.so")
+
+F64, F32, BF16, SAME = 0, 1, 2, 255
+OK, EINVAL, EDTYPE, ENOMEM, EHIP, ERANGE = 0, 1, 2, 3, 4, 5
+FLAG_INEXACT, FLAG_OVERFLOW, FLAG_NAN, FLAG_INF = 1, 2, 4, 8
+DIGITS = 68
+STATE_BYTES = 576
+OUT_BYTES = {F64: 8, F32: 4, BF16: 2}
+
+EXPORTED = [
+    "xsum_version", "xsum_last_error", "xsum_exact_sum", "xsum_exact_sum_f64",
+    "xsum_exact_sum_async", "xsum_exact_sum_async_blocks", "xsum_acc_zero",
+    "xsum_acc_add", "xsum_acc_merge", "xsum_acc_finalize",
+]
+
+
+class XsumError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("xsum status %d: %s" % (status, message))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            "libxsum.so is not built (expected at %s); run "
+            "`python paper_1605_05436_amd/build.py`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u64, i32, u32p = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, \
+        ctypes.POINTER(ctypes.c_uint32)
+    lib.xsum_version.restype = ctypes.c_char_p
+    lib.xsum_version.argtypes = []
+    lib.xsum_last_error.restype = ctypes.c_char_p
+    lib.xsum_last_error.argtypes = []
+    lib.xsum_exact_sum.restype = i32
+    lib.xsum_exact_sum.argtypes = [vp, u64, i32, i32, vp, u32p, vp]
+    lib.xsum_exact_sum_f64.restype = ctypes.c_double
+    lib.xsum_exact_sum_f64.argtypes = [vp, u64, i32]
+    lib.xsum_exact_sum_async.restype = i32
+    lib.xsum_exact_sum_async.argtypes = [vp, u64, i32, i32, vp, vp, vp, vp]
+    lib.xsum_exact_sum_async_blocks.restype = i32
+    lib.xsum_exact_sum_async_blocks.argtypes = [vp, u64, i32, i32, vp, vp, vp,
+                                                i32, vp]
+    lib.xsum_acc_zero.restype = i32
+    lib.xsum_acc_zero.argtypes = [vp, u64, vp]
+    lib.xsum_acc_add.restype = i32
+    lib.xsum_acc_add.argtypes = [vp, vp, u64, i32, vp]
+    lib.xsum_acc_merge.restype = i32
+    lib.xsum_acc_merge.argtypes = [vp, vp, vp]
+    lib.xsum_acc_finalize.restype = i32
+    lib.xsum_acc_finalize.argtypes = [vp, i32, vp, vp, vp]
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status):
+    if status != OK:
+        raise XsumError(status, xsum_last_error())
+
+
+def _p(x):
+    return ctypes.c_void_p(int(x)) if x else None
+
+
+def xsum_version():
+    return _lib.xsum_version().decode()
+
+
+def xsum_last_error():
+    return _lib.xsum_last_error().decode()
+
+
+def xsum_exact_sum(x, n, dtype, out_dtype=SAME, stream=0):
+    """Blocking exact sum of n elements at device address x.
+    Returns (result bit pattern as int, flags)."""
+    out = ctypes.c_uint64(0)
+    flags = ctypes.c_uint32(0)
+    _check(_lib.xsum_exact_sum(_p(x), n, dtype, out_dtype, ctypes.byref(out),
+                               ctypes.byref(flags), _p(stream)))
+    ob = OUT_BYTES[(F64 if dtype == F64 else F32) if out_dtype == SAME else out_dtype]
+    return out.value & ((1 << (8 * ob)) - 1), flags.value
+
+
+def xsum_exact_sum_f64(x, n, dtype):
+    return _lib.xsum_exact_sum_f64(_p(x), n, dtype)
+
+
+def xsum_exact_sum_async(x, n, dtype, out_dtype, out, flags, scratch, stream=0):
+    _check(_lib.xsum_exact_sum_async(_p(x), n, dtype, out_dtype, _p(out),
+                                     _p(flags), _p(scratch), _p(stream)))
+
+
+def xsum_exact_sum_async_blocks(x, n, dtype, out_dtype, out, flags, scratch,
+                                blocks, stream=0):
+    _check(_lib.xsum_exact_sum_async_blocks(_p(x), n, dtype, out_dtype, _p(out),
+                                            _p(flags), _p(scratch), blocks,
+                                            _p(stream)))
+
+
+def xsum_acc_zero(acc, count, stream=0):
+    _check(_lib.xsum_acc_zero(_p(acc), count, _p(stream)))
+
+
+def xsum_acc_add(acc, x, n, dtype, stream=0):
+    _check(_lib.xsum_acc_add(_p(acc), _p(x), n, dtype, _p(stream)))
+
+
+def xsum_acc_merge(dst, src, stream=0):
+    _check(_lib.xsum_acc_merge(_p(dst), _p(src), _p(stream)))
+
+
+def xsum_acc_finalize(acc, out_dtype, out, flags, stream=0):
+    _check(_lib.xsum_acc_finalize(_p(acc), out_dtype, _p(out), _p(flags),
+                                  _p(stream)))
+
+
+# ----------------------------------------------------- torch marshalling --
+
+def stream_handle(stream=None):
+    """Raw hipStream_t of a torch stream (default: the current stream)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def dtype_of(tensor, dtype=None):
+    """Library dtype code for a tensor: float64/float32/bfloat16 by type; raw
+    bit-pattern tensors (integer types) need an explicit dtype."""
+    import torch
+    if dtype is not None:
+        return dtype
+    m = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+    if tensor.dtype not in m:
+        raise ValueError("pass dtype= for a tensor of type %s" % tensor.dtype)
+    return m[tensor.dtype]
+
+
+def element_count(tensor, dtype):
+    return tensor.numel() * tensor.element_size() // {F64: 8, F32: 4, BF16: 2}[dtype]
+
+
+def exact_sum(tensor, dtype=None, out_dtype=SAME, stream=None):
+    """Blocking exact sum of a contiguous device tensor.
+    Returns (result bit pattern, flags)."""
+    if not tensor.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    d = dtype_of(tensor, dtype)
+    return xsum_exact_sum(tensor.data_ptr(), element_count(tensor, d), d,
+                          out_dtype, stream_handle(stream))
+
+
+def new_states(count=1, device="cuda", stream=None):
+    """count zeroed xsum_acc_t states in a device uint8 tensor [count, 576]."""
+    import torch
+    t = torch.empty((count, STATE_BYTES), dtype=torch.uint8, device=device)
+    xsum_acc_zero(t.data_ptr(), count, stream_handle(stream))
+    return t

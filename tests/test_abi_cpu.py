@@ -1,0 +1,102 @@
+"""The C-ABI library loads on a machine without a GPU, exports every function
+that include/xsum.h declares, and rejects bad arguments before touching the
+device (no compute calls here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xsum.h")
+LIB = os.path.join(ROOT, "paper_1605_05436_amd", "libxsum.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(xsum_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libxsum.so is not built; run __graft_entry__.build()")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("xsum_exact_sum", "xsum_exact_sum_async", "xsum_acc_add",
+                 "xsum_acc_merge", "xsum_acc_finalize", "xsum_acc_zero",
+                 "xsum_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    import paper_1605_05436_amd as xs
+    assert sorted(xs.EXPORTED) == declared_functions()
+    for n in declared_functions():
+        assert callable(getattr(xs, n))
+
+
+def test_struct_size_matches_header(lib):
+    import paper_1605_05436_amd as xs
+    assert xs.STATE_BYTES == 68 * 8 + 4 + 4 + 3 * 8
+
+
+def _err(lib):
+    lib.xsum_last_error.restype = ctypes.c_char_p
+    return lib.xsum_last_error().decode()
+
+
+def test_bad_dtype_is_rejected_on_the_host(lib):
+    out = ctypes.c_uint64()
+    lib.xsum_exact_sum.restype = ctypes.c_int
+    st = lib.xsum_exact_sum(ctypes.c_void_p(4096), ctypes.c_uint64(10), 7, 255,
+                            ctypes.byref(out), None, None)
+    assert st == 2 and "dtype" in _err(lib)
+
+
+def test_null_and_misaligned_inputs_are_rejected(lib):
+    out = ctypes.c_uint64()
+    lib.xsum_exact_sum.restype = ctypes.c_int
+    st = lib.xsum_exact_sum(None, ctypes.c_uint64(10), 0, 255, ctypes.byref(out),
+                            None, None)
+    assert st == 1 and "NULL" in _err(lib)
+    st = lib.xsum_exact_sum(ctypes.c_void_p(4100), ctypes.c_uint64(10), 0, 255,
+                            ctypes.byref(out), None, None)
+    assert st == 1 and "aligned" in _err(lib)
+    st = lib.xsum_exact_sum(ctypes.c_void_p(4096), ctypes.c_uint64(10), 0, 255,
+                            None, None, None)
+    assert st == 1
+
+
+def test_bad_output_dtype_and_null_state(lib):
+    lib.xsum_exact_sum_async.restype = ctypes.c_int
+    st = lib.xsum_exact_sum_async(ctypes.c_void_p(4096), ctypes.c_uint64(1), 0, 9,
+                                  ctypes.c_void_p(8192), None, ctypes.c_void_p(16384),
+                                  None)
+    assert st == 2
+    st = lib.xsum_exact_sum_async(ctypes.c_void_p(4096), ctypes.c_uint64(1), 0, 0,
+                                  ctypes.c_void_p(8192), None, None, None)
+    assert st == 1
+    lib.xsum_acc_add.restype = ctypes.c_int
+    assert lib.xsum_acc_add(None, ctypes.c_void_p(4096), ctypes.c_uint64(1), 0, None) == 1
+    lib.xsum_acc_merge.restype = ctypes.c_int
+    assert lib.xsum_acc_merge(None, None, None) == 1
+    lib.xsum_acc_finalize.restype = ctypes.c_int
+    assert lib.xsum_acc_finalize(ctypes.c_void_p(4096), 3, ctypes.c_void_p(8192),
+                                 None, None) == 2
+    lib.xsum_exact_sum_async_blocks.restype = ctypes.c_int
+    st = lib.xsum_exact_sum_async_blocks(ctypes.c_void_p(4096), ctypes.c_uint64(1), 0, 0,
+                                         ctypes.c_void_p(8192), None,
+                                         ctypes.c_void_p(16384), -1, None)
+    assert st == 1
