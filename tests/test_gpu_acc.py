@@ -1,0 +1,129 @@
+"""GPU parity of the accumulator interface: xsum_acc_zero / add / merge /
+finalize.  A state built from any split of the input, in any order, rounds to
+the oracle's result; the exported digits equal the oracle's exact integer."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_helpers import FMT_CODE, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1605_05436_amd  # noqa: F401
+
+
+def _finalize(st, out_fmt):
+    import torch
+    import paper_1605_05436_amd as xs
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    xs.xsum_acc_finalize(st.data_ptr(), FMT_CODE[out_fmt], out.data_ptr(),
+                         fl.data_ptr(), xs.stream_handle())
+    torch.cuda.synchronize()
+    ob = xs.OUT_BYTES[FMT_CODE[out_fmt]]
+    return int(out.cpu().numpy().view(np.uint64)[0]) & ((1 << (8 * ob)) - 1), int(fl.cpu()[0])
+
+
+def _state_int(st):
+    """Exact integer (units 2^-1074) held by a state, and its special bits."""
+    raw = st.cpu().numpy().reshape(-1)
+    digits = raw[:68 * 8].view(np.int64).tolist()
+    special = int(raw[68 * 8:68 * 8 + 4].view(np.uint32)[0])
+    return sum(d << (32 * j) for j, d in enumerate(digits)), special
+
+
+def _add(st, bits, fmt):
+    import paper_1605_05436_amd as xs
+    t = to_device(bits)
+    xs.xsum_acc_add(st.data_ptr(), t.data_ptr() if len(bits) else 0, len(bits),
+                    FMT_CODE[fmt], xs.stream_handle())
+    return t  # keep alive until the stream is synchronised
+
+
+def test_chunked_adds_equal_one_sum_and_state_is_exact():
+    import torch
+    import paper_1605_05436_amd as xs
+    bits, _ = workloads.config2(log2n=20, seed=4)
+    st = xs.new_states(1)
+    keep = []
+    cuts = [0, 1, 17, 4096, 100_000, 333_333, 700_001, len(bits)]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        keep.append(_add(st, bits[a:b], "f64"))
+    torch.cuda.synchronize()
+    exact = oracle.exact_sum_binned(bits, "f64")[0]
+    total, special = _state_int(st)
+    assert total == exact.total and special == 0
+    # canonical digits: 0..66 in [0, 2^32), top in {-1, 0}
+    digits = st.cpu().numpy().reshape(-1)[:68 * 8].view(np.int64)
+    assert np.all((digits[:67] >= 0) & (digits[:67] < 2 ** 32))
+    assert digits[67] in (0, -1)
+    for out_fmt in ("f64", "f32", "bf16"):
+        assert _finalize(st, out_fmt) == tuple(oracle.finish(exact, out_fmt))
+
+
+def test_merge_of_split_states_and_mixed_formats():
+    import torch
+    import paper_1605_05436_amd as xs
+    parts = [("f64", workloads.family("mixed", 50_001, 2000, seed=1)),
+             ("f32", workloads.family("mixed", 70_003, 250, seed=2, fmt="f32")),
+             ("bf16", np.zeros(0, dtype=np.uint16)),
+             ("bf16", workloads.family("mixed", 9_999, 250, seed=4, fmt="bf16")),
+             ("f64", np.array([0x7FF0000000000000], dtype=np.uint64))]
+    sts = xs.new_states(len(parts))
+    keep = []
+    exact = oracle.ExactSum()
+    for i, (fmt, bits) in enumerate(parts):
+        keep.append(_add(sts[i], bits, fmt))
+        exact = exact.merge(oracle.exact_sum(bits, fmt))
+    total = xs.new_states(1)
+    for i in reversed(range(len(parts))):
+        xs.xsum_acc_merge(total.data_ptr(), sts[i].data_ptr(), xs.stream_handle())
+    torch.cuda.synchronize()
+    assert _finalize(total, "f64") == tuple(oracle.finish(exact, "f64"))
+    # without the infinity
+    fin = oracle.ExactSum()
+    total2 = xs.new_states(1)
+    for i, (fmt, bits) in enumerate(parts[:-1]):
+        xs.xsum_acc_merge(total2.data_ptr(), sts[i].data_ptr(), xs.stream_handle())
+        fin = fin.merge(oracle.exact_sum(bits, fmt))
+    torch.cuda.synchronize()
+    assert _state_int(total2) == (fin.total, 0)
+    for out_fmt in ("f64", "f32"):
+        assert _finalize(total2, out_fmt) == tuple(oracle.finish(fin, out_fmt))
+
+
+def test_many_adds_keep_headroom():
+    """Thousands of adds of huge values into one state stay exact (the state
+    is carry-normalised after every add)."""
+    import torch
+    import paper_1605_05436_amd as xs
+    dmax = np.full(4096, workloads.DBL_MAX_BITS, dtype=np.uint64)
+    t = to_device(dmax)
+    st = xs.new_states(1)
+    reps = 2000
+    for _ in range(reps):
+        xs.xsum_acc_add(st.data_ptr(), t.data_ptr(), len(dmax), 0, xs.stream_handle())
+    torch.cuda.synchronize()
+    one = oracle.exact_sum(dmax[:1], "f64").total
+    total, _ = _state_int(st)
+    assert total == one * 4096 * reps
+    assert _finalize(st, "f64") == (0x7FF0000000000000, oracle.FLAG_OVERFLOW | oracle.FLAG_INEXACT)
+
+
+def test_zero_resets_many_states():
+    import torch
+    import paper_1605_05436_amd as xs
+    sts = xs.new_states(5)
+    keep = [_add(sts[i], workloads.config1(1000 + i, seed=i), "f64") for i in range(5)]
+    xs.xsum_acc_zero(sts.data_ptr(), 5, xs.stream_handle())
+    torch.cuda.synchronize()
+    assert not sts.cpu().numpy().any()
+    del keep
