@@ -47,12 +47,16 @@ def ulps_between(a, b):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-torch-sum", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, run one device copy of the input "
+                         "(a plain copy kernel of known size, for scaling "
+                         "profiler byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -159,6 +163,13 @@ def main():
                             "error_ulps": ulps_between(tval, exact_val),
                             "rel_error": (abs(tval - exact_val) / abs(exact_val)
                                           if exact_val else None)}
+
+    if args.copy_calibration:
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = {"read": n * 8, "write": n * 8}
+        del y
 
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = {"value": round(n / cpu_s / 1e9, 4),

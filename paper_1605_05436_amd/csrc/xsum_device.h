@@ -69,19 +69,18 @@ template <> struct Geo<XSUM_BF16> {
 
 __device__ __forceinline__ void lds_add(uint64_t *p, uint64_t v)
 {
-    // Each column belongs to one lane, so wavefront scope suffices; the
-    // result is unused, so this is a no-return ds_add_u64.
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    // The result is unused, so this is a no-return ds_add_u64.
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ uint64_t lds_load(uint64_t *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ void lds_store(uint64_t *p, uint64_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Special-value bits of a state: bit 0 NaN, bit 1 +inf, bit 2 -inf.

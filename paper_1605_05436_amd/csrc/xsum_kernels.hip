@@ -31,13 +31,14 @@ namespace xsum {
 // x: first element; head elements precede the 16-byte-aligned vector part
 // of nvec 16-byte vectors, followed by tail elements.
 //
-// binary64 columns are carry-normalised every kNormTiles tiles: between two
-// normalisations a lane adds at most kNormTiles*U*2 + U*2 + 2 elements (full
-// tiles, the partial tile, head and tail), each adding below 2^32 + 2^52 to
-// a digit that started below 2^32; with U = 16 and kNormTiles = 32 that is
-// at most 1058 elements, so every entry stays below 2^63 and its high word
-// below 2^31 in magnitude, as the block merge assumes.
-template <int FMT, int WAVES, int U>
+// binary64 columns are carry-normalised after every pair of full tiles that
+// brings the count of tiles since the last normalisation to kNormTiles or
+// more.  Between two normalisations a column therefore receives at most
+// (kNormTiles + 1) full tiles, one partial tile and a head/tail element,
+// fewer than (kNormTiles + 2)*U*2 + 2 < 2047 elements, each adding below
+// 2^32 + 2^52 to a digit that started below 2^32: every entry stays below
+// 2^63 and its high word below 2^31 in magnitude, as the block merge assumes.
+template <int FMT, int WAVES, int U, bool WAVE_CONTIG>
 __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
     const uint8_t *__restrict__ x, uint32_t head, uint64_t nvec,
     uint32_t tail, xsum_acc_t *acc, Finish fin)
@@ -45,8 +46,8 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
     using G = Geo<FMT>;
     constexpr int kThreads = WAVES * 64;
     constexpr uint64_t kTile = (uint64_t)kThreads * U;  // vectors per block step
-    constexpr int kNormTiles = 32;
-    static_assert(FMT != XSUM_F64 || (kNormTiles + 1) * U * 2 + 2 < 2047,
+    constexpr int kNormTiles = 512 / U;
+    static_assert(FMT != XSUM_F64 || (kNormTiles + 2) * U * 2 + 2 < 2047,
                   "binary64 column headroom");
     __shared__ uint64_t cols[WAVES][G::kN][64];
     __shared__ int64_t blk[kDigits];
@@ -55,11 +56,15 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t *col = &cols[wave][0][lane];
+    // vector j of this thread within a tile: interleaved across the block, or
+    // a contiguous 64*U-vector run per wave
+    const uint64_t my0 = WAVE_CONTIG ? (uint64_t)wave * 64 * U + lane : (uint64_t)tid;
+    constexpr uint64_t kJStride = WAVE_CONTIG ? 64 : kThreads;
 #pragma unroll
     for (int d = 0; d < G::kN; ++d)
         col[d * 64] = 0;
-    if (tid < kDigits)
-        blk[tid] = 0;
+    for (int d = tid; d < kDigits; d += kThreads)
+        blk[d] = 0;
     if (tid == 0)
         blk_spec = 0;
     uint32_t spec = 0;
@@ -73,14 +78,14 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
         vec4u qa[U], qb[U];
 #pragma unroll
         for (int j = 0; j < U; ++j)
-            qa[j] = __builtin_nontemporal_load(v + tb + j * kThreads + tid);
+            qa[j] = __builtin_nontemporal_load(v + tb + my0 + j * kJStride);
         for (;;) {
             uint64_t nb = tb + gstep;
             bool more = nb + kTile <= nvec;
             if (more) {
 #pragma unroll
                 for (int j = 0; j < U; ++j)
-                    qb[j] = __builtin_nontemporal_load(v + nb + j * kThreads + tid);
+                    qb[j] = __builtin_nontemporal_load(v + nb + my0 + j * kJStride);
             }
             add_tile<FMT, U>(qa, col, spec);
             tb = nb;
@@ -91,7 +96,7 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
             if (more) {
 #pragma unroll
                 for (int j = 0; j < U; ++j)
-                    qa[j] = __builtin_nontemporal_load(v + nb + j * kThreads + tid);
+                    qa[j] = __builtin_nontemporal_load(v + nb + my0 + j * kJStride);
             }
             add_tile<FMT, U>(qb, col, spec);
             tb = nb;
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
     // At most one partial tile exists (the last); its owner finishes it.
     if (tb < nvec) {
         for (int j = 0; j < U; ++j) {
-            const uint64_t i = tb + (uint64_t)j * kThreads + tid;
+            const uint64_t i = tb + my0 + (uint64_t)j * kJStride;
             vec4u q[1] = {{0u, 0u, 0u, 0u}};
             if (i < nvec)
                 q[0] = __builtin_nontemporal_load(v + i);
@@ -134,10 +139,10 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
     __syncthreads();
 
     // Grid merge: add the block's non-zero digits into the global state.
-    if (tid < kDigits) {
-        const int64_t dv = blk[tid];
+    for (int d = tid; d < kDigits; d += kThreads) {
+        const int64_t dv = blk[d];
         if (dv)
-            atomicAdd((unsigned long long *)&acc->digit[tid], (unsigned long long)dv);
+            atomicAdd((unsigned long long *)&acc->digit[d], (unsigned long long)dv);
     }
     if (tid == 0 && blk_spec)
         atomicOr(&acc->special, blk_spec);
@@ -210,16 +215,36 @@ int element_size(int dtype)
     return dtype == XSUM_F64 ? 8 : dtype == XSUM_F32 ? 4 : 2;
 }
 
-// Launch shape: 4-wave blocks.  A binary64 column is 66 x 64 x 8 B = 33 KiB
-// per wave, so one block fills a CU's LDS (160 KiB); the 33-bin binary32
-// columns take 17 KiB per wave, two blocks per CU.
-static constexpr int kWaves = 4;
-template <int FMT> struct Unroll { static constexpr int value = 16; };
-template <> struct Unroll<XSUM_BF16> { static constexpr int value = 8; };
+// Launch shapes (measured on MI355X with the timing harness, config-2-like
+// data): a binary64 column is 66 x 64 x 8 B = 33 KiB per wave, so two 2-wave
+// blocks fill a CU's 160 KiB of LDS; the 33-bin binary32 columns take 17 KiB
+// per wave.  Each wave keeps U 16-byte loads per lane in flight while it adds
+// the previous U; wave-contiguous tiles give each wave its own 64*U-vector
+// stream.
+template <int FMT> struct Shape_;
+template <> struct Shape_<XSUM_F64> {
+    static constexpr int kWaves = 2, kUnroll = 16, kBlocksPerCu = 2;
+    static constexpr bool kWaveContig = true;
+};
+template <> struct Shape_<XSUM_F32> {
+    static constexpr int kWaves = 2, kUnroll = 16, kBlocksPerCu = 4;
+    static constexpr bool kWaveContig = true;
+};
+template <> struct Shape_<XSUM_BF16> {
+    static constexpr int kWaves = 1, kUnroll = 8, kBlocksPerCu = 8;
+    static constexpr bool kWaveContig = true;
+};
 
 int persistent_blocks(int dtype, int cu_count)
 {
-    return dtype == XSUM_F64 ? cu_count : 2 * cu_count;
+    switch (dtype) {
+    case XSUM_F64:
+        return Shape_<XSUM_F64>::kBlocksPerCu * cu_count;
+    case XSUM_F32:
+        return Shape_<XSUM_F32>::kBlocksPerCu * cu_count;
+    default:
+        return Shape_<XSUM_BF16>::kBlocksPerCu * cu_count;
+    }
 }
 
 template <int FMT>
@@ -228,6 +253,7 @@ static hipError_t launch_fmt(const void *x, uint64_t n, xsum_acc_t *acc,
                              const Shape &shape, hipStream_t stream)
 {
     using G = Geo<FMT>;
+    using S = Shape_<FMT>;
     const uintptr_t addr = (uintptr_t)x;
     uint64_t head = ((16 - (addr & 15)) & 15) / G::kBytes;
     if (head > n)
@@ -235,8 +261,7 @@ static hipError_t launch_fmt(const void *x, uint64_t n, xsum_acc_t *acc,
     const uint64_t rest = n - head;
     const uint64_t nvec = rest / G::kPerVec;
     const uint64_t tail = rest - nvec * G::kPerVec;
-    constexpr int kUnroll = Unroll<FMT>::value;
-    const uint64_t tile = (uint64_t)kWaves * 64 * kUnroll;
+    const uint64_t tile = (uint64_t)S::kWaves * 64 * S::kUnroll;
     const uint64_t tiles = (nvec + tile - 1) / tile;
     uint64_t blocks = shape.blocks > 0 ? (uint64_t)shape.blocks
                                        : (uint64_t)persistent_blocks(FMT, cu_count);
@@ -244,9 +269,9 @@ static hipError_t launch_fmt(const void *x, uint64_t n, xsum_acc_t *acc,
         blocks = tiles;
     if (blocks < 1)
         blocks = 1;
-    hipLaunchKernelGGL((accumulate_kernel<FMT, kWaves, kUnroll>), dim3((unsigned)blocks),
-                       dim3(kWaves * 64), 0, stream, (const uint8_t *)x,
-                       (uint32_t)head, nvec, (uint32_t)tail, acc, fin);
+    hipLaunchKernelGGL((accumulate_kernel<FMT, S::kWaves, S::kUnroll, S::kWaveContig>),
+                       dim3((unsigned)blocks), dim3(S::kWaves * 64), 0, stream,
+                       (const uint8_t *)x, (uint32_t)head, nvec, (uint32_t)tail, acc, fin);
     return hipGetLastError();
 }
 
