@@ -162,6 +162,102 @@ xsum_status_t xsum_acc_finalize(const xsum_acc_t *acc, int out_dtype,
                                 void *out_dev, uint32_t *flags_dev,
                                 void *stream);
 
+/* ------------------------------------------------------------------------
+ * Segmented sums: many independent exact sums of uneven lengths and mixed
+ * formats in one persistent kernel launch (Section 6: each reducer sums its
+ * own inputs into a superaccumulator; long inputs are summed per chunk and
+ * the chunk states merged and rounded once).
+ * ------------------------------------------------------------------------ */
+
+/* One segment: `length` elements of format `dtype` starting `byte_offset`
+ * bytes after the run's base pointer.  byte_offset must be a multiple of the
+ * element size.  Same layout on host and device (24 bytes). */
+typedef struct xsum_segment {
+    uint64_t byte_offset;
+    uint64_t length;
+    uint32_t dtype;     /* XSUM_F64, XSUM_F32 or XSUM_BF16 */
+    uint32_t reserved;  /* ignored */
+} xsum_segment_t;
+
+/* Tuning knobs of a plan; 0 in any field means the library default.
+ *   lane_max[d]   segments of dtype d with at most this many elements are
+ *                 summed one per lane (default 4096 / 8192 / 16384 for
+ *                 binary64 / binary32 / bfloat16); longer ones are split into
+ *                 chunks summed by whole waves
+ *   chunk_vectors 16-byte vectors per chunk (default 8192, range [64, 2^26])
+ *   blocks_per_cu resident one-wave workgroups per compute unit (default 4,
+ *                 range [1, 16]) */
+typedef struct xsum_seg_tuning {
+    uint64_t lane_max[3];
+    uint64_t chunk_vectors;
+    uint32_t blocks_per_cu;
+    uint32_t reserved;
+} xsum_seg_tuning_t;
+
+/* Plan statistics. */
+typedef struct xsum_plan_info {
+    uint64_t nseg, lane_segments, chunked_segments, chunks, work_items;
+    uint64_t lane_max[3], chunk_vectors, workspace_bytes;
+    uint32_t blocks, reserved;
+} xsum_plan_info_t;
+
+typedef struct xsum_plan xsum_plan_t;  /* opaque, owned by the library */
+
+/*
+ * Build a plan from host descriptors (copied; the caller may free them).
+ * Segments are bucketed by format and length: short ones are grouped 64 to a
+ * wave, one per lane, longest first; long ones are cut into chunks, each with
+ * a state slot in the workspace.  The plan lives on the current device.
+ *   out_dtype  XSUM_SAME (binary64 for binary64 segments, binary32 for the
+ *              others) or one output format for every segment
+ *   tuning     may be NULL
+ * Errors: XSUM_EINVAL (NULL pointers, misaligned offsets), XSUM_EDTYPE,
+ * XSUM_ERANGE (more than 2^31-1 segments, a length above 2^40, bad tuning),
+ * XSUM_ENOMEM / XSUM_EHIP.
+ */
+xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs_host,
+                                  uint64_t nseg, int out_dtype,
+                                  const xsum_seg_tuning_t *tuning,
+                                  xsum_plan_t **plan);
+void xsum_plan_destroy(xsum_plan_t *plan);
+xsum_status_t xsum_plan_get_info(const xsum_plan_t *plan,
+                                 xsum_plan_info_t *info);
+
+/* Bytes of device workspace a run of this plan needs (control words plus one
+ * 576-byte state per chunked segment). */
+size_t xsum_segmented_workspace_size(const xsum_plan_t *plan);
+
+/* Zero a workspace (a fill kernel on `stream`, no memset).  Needed once after
+ * allocation; every completed run leaves the workspace zeroed again.
+ * ws_bytes must be a multiple of 8. */
+xsum_status_t xsum_segmented_workspace_init(void *workspace, size_t ws_bytes,
+                                            void *stream);
+
+/*
+ * Run a plan: one kernel launch on `stream`, asynchronous.
+ *   base       device, 16-byte aligned; segment i starts at base + offset_i
+ *   out        device, nseg 8-byte slots; slot i receives segment i's result
+ *              bit pattern zero-extended to 64 bits
+ *   flags      device, nseg uint32 (XSUM_FLAG_* per segment), may be NULL
+ *   workspace  device, >= xsum_segmented_workspace_size(plan) bytes, zeroed
+ *              once by xsum_segmented_workspace_init; runs sharing a
+ *              workspace must be ordered
+ * The launch contains no memset and no host synchronisation, so it may be
+ * captured into a graph and replayed.
+ */
+xsum_status_t xsum_segmented_run(const xsum_plan_t *plan, const void *base,
+                                 void *out, uint32_t *flags, void *workspace,
+                                 size_t ws_bytes, void *stream);
+
+/* Capture one xsum_segmented_run into an instantiated HIP graph (returned as
+ * hipGraphExec_t in *graph_exec); replay it with xsum_graph_launch. */
+xsum_status_t xsum_segmented_capture(const xsum_plan_t *plan, const void *base,
+                                     void *out, uint32_t *flags,
+                                     void *workspace, size_t ws_bytes,
+                                     void **graph_exec);
+xsum_status_t xsum_graph_launch(void *graph_exec, void *stream);
+void xsum_graph_destroy(void *graph_exec);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,26 @@ EXPORTED = [
     "xsum_version", "xsum_last_error", "xsum_exact_sum", "xsum_exact_sum_f64",
     "xsum_exact_sum_async", "xsum_exact_sum_async_blocks", "xsum_acc_zero",
     "xsum_acc_add", "xsum_acc_merge", "xsum_acc_finalize",
+    "xsum_segmented_plan", "xsum_plan_destroy", "xsum_plan_get_info",
+    "xsum_segmented_workspace_size", "xsum_segmented_workspace_init",
+    "xsum_segmented_run", "xsum_segmented_capture", "xsum_graph_launch",
+    "xsum_graph_destroy",
 ]
+
+
+class SegTuning(ctypes.Structure):
+    """xsum_seg_tuning_t (0 = library default in every field)."""
+    _fields_ = [("lane_max", ctypes.c_uint64 * 3), ("chunk_vectors", ctypes.c_uint64),
+                ("blocks_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class PlanInfo(ctypes.Structure):
+    """xsum_plan_info_t."""
+    _fields_ = [("nseg", ctypes.c_uint64), ("lane_segments", ctypes.c_uint64),
+                ("chunked_segments", ctypes.c_uint64), ("chunks", ctypes.c_uint64),
+                ("work_items", ctypes.c_uint64), ("lane_max", ctypes.c_uint64 * 3),
+                ("chunk_vectors", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
+                ("blocks", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class XsumError(RuntimeError):
@@ -67,6 +86,25 @@ def _load():
     lib.xsum_acc_merge.argtypes = [vp, vp, vp]
     lib.xsum_acc_finalize.restype = i32
     lib.xsum_acc_finalize.argtypes = [vp, i32, vp, vp, vp]
+    lib.xsum_segmented_plan.restype = i32
+    lib.xsum_segmented_plan.argtypes = [vp, u64, i32, vp, ctypes.POINTER(vp)]
+    lib.xsum_plan_destroy.restype = None
+    lib.xsum_plan_destroy.argtypes = [vp]
+    lib.xsum_plan_get_info.restype = i32
+    lib.xsum_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.xsum_segmented_workspace_size.restype = ctypes.c_size_t
+    lib.xsum_segmented_workspace_size.argtypes = [vp]
+    lib.xsum_segmented_workspace_init.restype = i32
+    lib.xsum_segmented_workspace_init.argtypes = [vp, ctypes.c_size_t, vp]
+    lib.xsum_segmented_run.restype = i32
+    lib.xsum_segmented_run.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.xsum_segmented_capture.restype = i32
+    lib.xsum_segmented_capture.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t,
+                                           ctypes.POINTER(vp)]
+    lib.xsum_graph_launch.restype = i32
+    lib.xsum_graph_launch.argtypes = [vp, vp]
+    lib.xsum_graph_destroy.restype = None
+    lib.xsum_graph_destroy.argtypes = [vp]
     return lib
 
 
@@ -134,6 +172,61 @@ def xsum_acc_finalize(acc, out_dtype, out, flags, stream=0):
                                   _p(stream)))
 
 
+def xsum_segmented_plan(segs, out_dtype=SAME, tuning=None):
+    """Plan for the segment descriptors `segs` (a numpy array with fields
+    byte_offset u8, length u8, dtype u4, reserved u4, 24 bytes each, on the
+    host).  Returns an opaque plan handle (int); free with xsum_plan_destroy."""
+    import numpy as np
+    a = np.ascontiguousarray(segs)
+    if a.dtype.itemsize != 24:
+        raise ValueError("segment descriptors must be 24-byte records")
+    handle = ctypes.c_void_p()
+    _check(_lib.xsum_segmented_plan(a.ctypes.data if a.size else None, a.size,
+                                    out_dtype, ctypes.byref(tuning) if tuning else None,
+                                    ctypes.byref(handle)))
+    return handle.value
+
+
+def xsum_plan_destroy(plan):
+    _lib.xsum_plan_destroy(_p(plan))
+
+
+def xsum_plan_get_info(plan):
+    info = PlanInfo()
+    _check(_lib.xsum_plan_get_info(_p(plan), ctypes.byref(info)))
+    d = {k: getattr(info, k) for k, _ in PlanInfo._fields_ if k != "reserved"}
+    d["lane_max"] = list(info.lane_max)
+    return d
+
+
+def xsum_segmented_workspace_size(plan):
+    return int(_lib.xsum_segmented_workspace_size(_p(plan)))
+
+
+def xsum_segmented_workspace_init(ws, nbytes, stream=0):
+    _check(_lib.xsum_segmented_workspace_init(_p(ws), nbytes, _p(stream)))
+
+
+def xsum_segmented_run(plan, base, out, flags, ws, ws_bytes, stream=0):
+    _check(_lib.xsum_segmented_run(_p(plan), _p(base), _p(out), _p(flags), _p(ws),
+                                   ws_bytes, _p(stream)))
+
+
+def xsum_segmented_capture(plan, base, out, flags, ws, ws_bytes):
+    g = ctypes.c_void_p()
+    _check(_lib.xsum_segmented_capture(_p(plan), _p(base), _p(out), _p(flags), _p(ws),
+                                       ws_bytes, ctypes.byref(g)))
+    return g.value
+
+
+def xsum_graph_launch(graph, stream=0):
+    _check(_lib.xsum_graph_launch(_p(graph), _p(stream)))
+
+
+def xsum_graph_destroy(graph):
+    _lib.xsum_graph_destroy(_p(graph))
+
+
 # ----------------------------------------------------- torch marshalling --
 
 def stream_handle(stream=None):
@@ -167,6 +260,42 @@ def exact_sum(tensor, dtype=None, out_dtype=SAME, stream=None):
     d = dtype_of(tensor, dtype)
     return xsum_exact_sum(tensor.data_ptr(), element_count(tensor, d), d,
                           out_dtype, stream_handle(stream))
+
+
+class SegmentedSum:
+    """A plan plus its device workspace, for repeated runs over one
+    descriptor set.  base/out/flags are device tensors or raw pointers."""
+
+    def __init__(self, segs, out_dtype=SAME, tuning=None, device="cuda", stream=None):
+        import torch
+        self.plan = xsum_segmented_plan(segs, out_dtype, tuning)
+        self.nseg = len(segs)
+        self.ws_bytes = max(8, xsum_segmented_workspace_size(self.plan))
+        self.workspace = torch.empty(self.ws_bytes // 8 + 1, dtype=torch.int64, device=device)
+        xsum_segmented_workspace_init(self.workspace.data_ptr(), self.ws_bytes,
+                                      stream_handle(stream))
+        self.info = xsum_plan_get_info(self.plan)
+
+    def run(self, base, out, flags=None, stream=None):
+        p = lambda t: (t.data_ptr() if hasattr(t, "data_ptr") else int(t)) if t is not None else 0
+        xsum_segmented_run(self.plan, p(base), p(out), p(flags), self.workspace.data_ptr(),
+                           self.ws_bytes, stream_handle(stream))
+
+    def capture(self, base, out, flags=None):
+        p = lambda t: (t.data_ptr() if hasattr(t, "data_ptr") else int(t)) if t is not None else 0
+        return xsum_segmented_capture(self.plan, p(base), p(out), p(flags),
+                                      self.workspace.data_ptr(), self.ws_bytes)
+
+    def close(self):
+        if self.plan:
+            xsum_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def new_states(count=1, device="cuda", stream=None):

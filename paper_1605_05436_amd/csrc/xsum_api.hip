@@ -142,7 +142,7 @@ xsum_status_t sum_async(const void *x, uint64_t n, int dtype, int out_dtype,
     int dev, cus;
     if ((st = current_cus(&dev, &cus)) != XSUM_OK)
         return st;
-    xsum::Finish fin{xsum::kRound, of, out_dev, flags_dev};
+    xsum::Finish fin{xsum::kRound, of, out_dev, flags_dev, 0};
     hipError_t e = xsum::launch_accumulate(x, n, dtype, scratch, fin, cus,
                                            xsum::Shape{blocks},
                                            (hipStream_t)stream);
@@ -152,6 +152,12 @@ xsum_status_t sum_async(const void *x, uint64_t n, int dtype, int out_dtype,
 }
 
 }  // namespace
+
+namespace xsum {
+xsum_status_t api_fail(xsum_status_t st, const std::string &msg) { return fail(st, msg); }
+xsum_status_t api_hip_fail(hipError_t e, const char *what) { return hip_fail(e, what); }
+xsum_status_t api_current_cus(int *dev, int *cus) { return current_cus(dev, cus); }
+}  // namespace xsum
 
 extern "C" {
 
@@ -197,7 +203,7 @@ xsum_status_t xsum_exact_sum(const void *x, uint64_t n, int dtype,
     if ((st = blocking_ws(dev, stream, &w)) != XSUM_OK)
         return st;
     std::lock_guard<std::mutex> lk(w->mu);
-    xsum::Finish fin{xsum::kRound, of, w->dev_out, (uint32_t *)(w->dev_out + 8)};
+    xsum::Finish fin{xsum::kRound, of, w->dev_out, (uint32_t *)(w->dev_out + 8), 0};
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = xsum::launch_accumulate(x, n, dtype, w->acc, fin, cus,
                                            xsum::Shape{0}, s);
@@ -244,7 +250,7 @@ xsum_status_t xsum_acc_add(xsum_acc_t *acc, const void *x, uint64_t n,
     int dev, cus;
     if ((st = current_cus(&dev, &cus)) != XSUM_OK)
         return st;
-    xsum::Finish fin{xsum::kKeep, XSUM_F64, nullptr, nullptr};
+    xsum::Finish fin{xsum::kKeep, XSUM_F64, nullptr, nullptr, 0};
     hipError_t e = xsum::launch_accumulate(x, n, dtype, acc, fin, cus,
                                            xsum::Shape{0}, (hipStream_t)stream);
     return e == hipSuccess ? XSUM_OK : hip_fail(e, "kernel launch");

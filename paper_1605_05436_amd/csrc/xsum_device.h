@@ -459,19 +459,34 @@ __device__ __forceinline__ uint64_t low_mask(int k)
 
 // Round canonical digits (output of normalise_wave) held by the wave.
 // Returns the bit pattern in every lane.
+// Result decided by special inputs (IEEE addition): any NaN, or +inf with
+// -inf, gives the quiet NaN; otherwise an infinity gives that infinity.
+// Returns false when no special value was seen.
+__device__ __forceinline__ bool special_result(uint32_t special,
+                                               const OutFormat &f,
+                                               uint64_t &bits, uint32_t &flags)
+{
+    if ((special & 1u) || ((special & 6u) == 6u)) {
+        flags = XSUM_FLAG_NAN | ((special & 6u) ? XSUM_FLAG_INF : 0u);
+        bits = fmt_qnan(f);
+        return true;
+    }
+    if (special & 6u) {
+        flags = XSUM_FLAG_INF;
+        bits = fmt_inf(f, (special & 4u) != 0);
+        return true;
+    }
+    return false;
+}
+
 static __device__ uint64_t round_wave(int64_t a, int64_t b, int lane,
                                uint32_t special, int out_fmt, uint32_t &flags)
 {
     const OutFormat f = out_format(out_fmt);
     flags = 0;
-    if ((special & 1u) || ((special & 6u) == 6u)) {
-        flags = XSUM_FLAG_NAN | ((special & 6u) ? XSUM_FLAG_INF : 0u);
-        return fmt_qnan(f);
-    }
-    if (special & 6u) {
-        flags = XSUM_FLAG_INF;
-        return fmt_inf(f, (special & 4u) != 0);
-    }
+    uint64_t sbits;
+    if (special_result(special, f, sbits, flags))
+        return sbits;
     const int64_t top = __shfl(b, 33, 64);
     const bool neg = top < 0;
     const bool is_digit_b = lane < 33;  // lane 33's b is the top digit
@@ -518,6 +533,82 @@ static __device__ uint64_t round_wave(int64_t a, int64_t b, int lane,
     return round_magnitude(neg, h, w[0], w[1], w[2], sticky, f, flags);
 }
 
+
+// ------------------------------------------------- per-lane rounding --
+//
+// A lane that summed a whole segment in its own column rounds it alone: one
+// upward pass over the digits propagates the carries (sequentially, as the
+// paper's back-to-front carry scan of Section 5 step 4 does), and two trackers
+// follow the pass, one reading the digits as a non-negative number and one as
+// the magnitude of a negative number (two's complement: the +1 ripples
+// through low zero digits).  Each tracker keeps the highest non-zero digit,
+// the two digits below it and whether anything lower is non-zero, which is
+// all the rounding step needs.
+
+struct TopTracker {
+    int h = -1;
+    uint32_t w2 = 0, w1 = 0, w0 = 0;
+    bool sticky = false;
+    uint32_t p1 = 0, p2 = 0;
+    bool orlow = false;
+
+    __device__ __forceinline__ void feed(int d, uint32_t u)
+    {
+        if (u) {
+            h = d;
+            w2 = u;
+            w1 = p1;
+            w0 = p2;
+            sticky = orlow;
+        }
+        orlow = orlow || (p2 != 0);
+        p2 = p1;
+        p1 = u;
+    }
+};
+
+struct LaneFinisher {
+    int64_t carry = 0;
+    uint32_t neg_c = 1;       // +1 of the two's complement, still rippling
+    TopTracker pos, neg;
+    int next = 0;             // digit index of the next feed
+
+    // Feed the next raw digit (any int64 with |d| < 2^62).
+    __device__ __forceinline__ void feed(int64_t raw)
+    {
+        const int64_t x = raw + carry;
+        const uint32_t u = (uint32_t)((uint64_t)x & kLow32);
+        carry = x >> 32;
+        pos.feed(next, u);
+        const uint32_t m = (~u) + neg_c;   // (2^32 - 1 - u + c) mod 2^32
+        neg_c = neg_c && (u == 0);
+        neg.feed(next, m);
+        ++next;
+    }
+
+    // Round after the last digit; the remaining carry is the signed top.
+    // digit0 is the grid index of the first fed digit.
+    __device__ __forceinline__ uint64_t round(uint32_t special, int out_fmt,
+                                              int digit0, uint32_t &flags)
+    {
+        const OutFormat f = out_format(out_fmt);
+        flags = 0;
+        uint64_t bits;
+        if (special_result(special, f, bits, flags))
+            return bits;
+        const int64_t top = carry;
+        const bool negative = top < 0;
+        if (!(top == 0 || top == -1) || (negative && neg.h < 0)) {
+            flags = XSUM_FLAG_OVERFLOW | XSUM_FLAG_INEXACT;
+            return fmt_inf(f, negative);
+        }
+        const TopTracker &t = negative ? neg : pos;
+        if (t.h < 0)
+            return 0;                                // exact zero -> +0
+        return round_magnitude(negative, digit0 + t.h, t.w2, t.w1, t.w0,
+                               t.sticky, f, flags);
+    }
+};
 
 __device__ __forceinline__ void store_result(void *out, int out_fmt,
                                              uint64_t bits)
@@ -566,7 +657,10 @@ static __device__ void finish_state(xsum_acc_t *acc, const Finish &fin, int lane
         uint32_t flags;
         const uint64_t bits = round_wave(a, b, lane, special, fin.out_fmt, flags);
         if (lane == 0) {
-            store_result(fin.out, fin.out_fmt, bits);
+            if (fin.out_slot8)
+                *(uint64_t *)fin.out = bits;
+            else
+                store_result(fin.out, fin.out_fmt, bits);
             if (fin.flags)
                 *fin.flags = flags;
             __hip_atomic_store(&acc->special, 0u, __ATOMIC_RELAXED,

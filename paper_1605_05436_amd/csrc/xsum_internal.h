@@ -20,6 +20,7 @@ struct Finish {
     int out_fmt;       // XSUM_F64 / XSUM_F32 / XSUM_BF16 (resolved, never SAME)
     void *out;         // device, result bit pattern (kRound only)
     uint32_t *flags;   // device, may be null (kRound only)
+    int out_slot8;     // nonzero: write the pattern zero-extended to 8 bytes
 };
 
 // Launch shape of the single-sum kernel.  blocks == 0 means "one resident
@@ -47,6 +48,9 @@ hipError_t launch_merge(xsum_acc_t *dst, const xsum_acc_t *src,
 // Zero count states with a fill kernel (no memset node, so the call can be
 // captured into a graph).
 hipError_t launch_zero(xsum_acc_t *acc, uint64_t count, hipStream_t stream);
+
+// Zero `words` 64-bit words with a fill kernel.
+hipError_t launch_zero_words(uint64_t *p, uint64_t words, hipStream_t stream);
 
 // Number of blocks a persistent single-sum grid uses for this format.
 int persistent_blocks(int dtype, int cu_count);

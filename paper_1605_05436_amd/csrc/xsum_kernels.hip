@@ -306,14 +306,18 @@ hipError_t launch_merge(xsum_acc_t *dst, const xsum_acc_t *src,
 
 hipError_t launch_zero(xsum_acc_t *acc, uint64_t count, hipStream_t stream)
 {
-    const uint64_t words = count * (sizeof(xsum_acc_t) / 8);
+    return launch_zero_words((uint64_t *)acc, count * (sizeof(xsum_acc_t) / 8), stream);
+}
+
+hipError_t launch_zero_words(uint64_t *p, uint64_t words, hipStream_t stream)
+{
     uint64_t blocks = (words + 255) / 256;
     if (blocks > 1024)
         blocks = 1024;
     if (blocks < 1)
         blocks = 1;
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
-                       (uint64_t *)acc, words);
+                       p, words);
     return hipGetLastError();
 }
 

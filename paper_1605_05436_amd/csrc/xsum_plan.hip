@@ -1,0 +1,336 @@
+// Host side of segmented sums: planning (bucketing segments into per-lane
+// groups and per-wave chunks), workspace sizing, launch and graph capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "xsum.h"
+#include "xsum_internal.h"
+#include "xsum_segmented.h"
+
+namespace xsum {
+hipError_t launch_segmented(const void *base, const SegDesc *segs,
+                            const SegTask *tasks, uint32_t ntasks,
+                            const uint32_t *perm, xsum_acc_t *states,
+                            SegCtl *ctl, int out_mode, uint64_t *out,
+                            uint32_t *flags, int blocks, hipStream_t stream);
+int segmented_blocks(int cu_count, int blocks_per_cu);
+uint64_t segmented_chunk_vectors();
+xsum_status_t api_fail(xsum_status_t st, const std::string &msg);
+xsum_status_t api_hip_fail(hipError_t e, const char *what);
+xsum_status_t api_current_cus(int *dev, int *cus);
+}  // namespace xsum
+
+struct xsum_plan {
+    int device = 0;
+    uint64_t nseg = 0;
+    int out_mode = XSUM_SAME;
+    xsum::SegDesc *d_segs = nullptr;
+    xsum::SegTask *d_tasks = nullptr;
+    uint32_t *d_perm = nullptr;
+    uint32_t ntasks = 0, nslots = 0;
+    int blocks = 0;
+    xsum_plan_info_t info{};
+};
+
+namespace {
+
+using xsum::api_fail;
+using xsum::api_hip_fail;
+
+constexpr int kPerVec[3] = {2, 4, 8};
+constexpr int kBytes[3] = {8, 4, 2};
+// Default per-lane limits: segments up to this many elements are summed one
+// per lane (32 KiB of input per lane).
+constexpr uint64_t kLaneMaxDefault[3] = {4096, 8192, 16384};
+
+void free_plan(xsum_plan *p)
+{
+    if (!p)
+        return;
+    if (p->d_segs)
+        (void)hipFree(p->d_segs);
+    if (p->d_tasks)
+        (void)hipFree(p->d_tasks);
+    if (p->d_perm)
+        (void)hipFree(p->d_perm);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
+                                  int out_dtype, const xsum_seg_tuning_t *tuning,
+                                  xsum_plan_t **plan_out)
+{
+    if (plan_out == nullptr)
+        return api_fail(XSUM_EINVAL, "plan_out is NULL");
+    *plan_out = nullptr;
+    if (nseg > 0 && segs == nullptr)
+        return api_fail(XSUM_EINVAL, "segment array is NULL with nseg > 0");
+    if (nseg >= (1ull << 31))
+        return api_fail(XSUM_ERANGE, "at most 2^31 - 1 segments per plan");
+    if (!(out_dtype == XSUM_SAME || out_dtype == XSUM_F64 || out_dtype == XSUM_F32 ||
+          out_dtype == XSUM_BF16))
+        return api_fail(XSUM_EDTYPE, "unknown output dtype " + std::to_string(out_dtype));
+    uint64_t lane_max[3];
+    for (int d = 0; d < 3; ++d)
+        lane_max[d] = kLaneMaxDefault[d];
+    uint64_t chunk_vectors = xsum::segmented_chunk_vectors();
+    int blocks_per_cu = 0;
+    if (tuning) {
+        for (int d = 0; d < 3; ++d)
+            if (tuning->lane_max[d])
+                lane_max[d] = tuning->lane_max[d];
+        if (tuning->chunk_vectors)
+            chunk_vectors = tuning->chunk_vectors;
+        blocks_per_cu = (int)tuning->blocks_per_cu;
+        if (lane_max[0] > (1u << 20) || lane_max[1] > (1u << 22) || lane_max[2] > (1u << 23))
+            return api_fail(XSUM_ERANGE, "lane_max too large");
+        if (chunk_vectors < 64 || chunk_vectors > (1u << 26))
+            return api_fail(XSUM_ERANGE, "chunk_vectors out of range [64, 2^26]");
+        if (blocks_per_cu < 0 || blocks_per_cu > 16)
+            return api_fail(XSUM_ERANGE, "blocks_per_cu out of range [0, 16]");
+    }
+    // validate descriptors, split into per-lane and chunked segments
+    std::vector<uint32_t> lane_ids[3];
+    std::vector<uint32_t> chunk_ids;
+    for (uint64_t i = 0; i < nseg; ++i) {
+        const uint32_t dt = segs[i].dtype;
+        if (dt > 2)
+            return api_fail(XSUM_EDTYPE, "segment " + std::to_string(i) + ": unknown dtype");
+        if (segs[i].byte_offset % (uint64_t)kBytes[dt] != 0)
+            return api_fail(XSUM_EINVAL, "segment " + std::to_string(i) +
+                                             ": offset not aligned to its element size");
+        if (segs[i].length > (1ull << 40))
+            return api_fail(XSUM_ERANGE, "segment " + std::to_string(i) + ": length above 2^40");
+        if (segs[i].length <= lane_max[dt])
+            lane_ids[dt].push_back((uint32_t)i);
+        else
+            chunk_ids.push_back((uint32_t)i);
+    }
+    struct HostTask {
+        xsum::SegTask t;
+        uint64_t cost;  // estimated time: vectors one lane walks through
+    };
+    std::vector<HostTask> tasks;
+    std::vector<uint32_t> perm;
+    // long segments: chunks of chunk_vectors 16-byte vectors, one state each
+    uint32_t slots = 0;
+    uint64_t nchunks_total = 0;
+    for (uint32_t id : chunk_ids) {
+        const uint32_t dt = segs[id].dtype;
+        const uint64_t L = segs[id].length;
+        uint64_t head = ((16 - (segs[id].byte_offset & 15)) & 15) / kBytes[dt];
+        if (head > L)
+            head = L;
+        const uint64_t nvs = (L - head) / kPerVec[dt];
+        uint64_t nch = (nvs + chunk_vectors - 1) / chunk_vectors;
+        if (nch == 0)
+            nch = 1;
+        if (nch >= (1ull << 32))
+            return api_fail(XSUM_ERANGE, "too many chunks in one segment");
+        for (uint64_t c = 0; c < nch; ++c) {
+            HostTask h{};
+            uint32_t fl = (c == 0 ? xsum::kChunkFirst : 0) | (c + 1 == nch ? xsum::kChunkLast : 0);
+            h.t.kind_dtype_flags = xsum::kChunk | (dt << 8) | (fl << 16);
+            h.t.a = id;
+            h.t.b = slots;
+            h.t.nchunks = (uint32_t)nch;
+            h.t.v0 = c * chunk_vectors;
+            h.t.nv = std::min(chunk_vectors, nvs - std::min(nvs, c * chunk_vectors));
+            h.cost = h.t.nv / 64 + 1;
+            tasks.push_back(h);
+        }
+        nchunks_total += nch;
+        ++slots;
+    }
+    // short segments: sorted by length (longest first), 64 per lane group
+    for (int dt = 0; dt < 3; ++dt) {
+        std::vector<uint32_t> &ids = lane_ids[dt];
+        std::stable_sort(ids.begin(), ids.end(), [&](uint32_t x, uint32_t y) {
+            return segs[x].length > segs[y].length;
+        });
+        for (size_t g = 0; g < ids.size(); g += 64) {
+            const size_t cnt = std::min<size_t>(64, ids.size() - g);
+            HostTask h{};
+            h.t.kind_dtype_flags = xsum::kLaneGroup | ((uint32_t)dt << 8);
+            h.t.a = (uint32_t)perm.size();
+            h.t.b = (uint32_t)cnt;
+            h.cost = segs[ids[g]].length / kPerVec[dt] + 1;
+            tasks.push_back(h);
+            perm.insert(perm.end(), ids.begin() + g, ids.begin() + g + cnt);
+        }
+    }
+    // longest work first, so the queue drains evenly
+    std::stable_sort(tasks.begin(), tasks.end(),
+                     [](const HostTask &x, const HostTask &y) { return x.cost > y.cost; });
+    if (tasks.size() >= (1ull << 32) - 4096)
+        return api_fail(XSUM_ERANGE, "too many work items");
+
+    int dev, cus;
+    xsum_status_t st = xsum::api_current_cus(&dev, &cus);
+    if (st != XSUM_OK)
+        return st;
+    xsum_plan *p = new xsum_plan();
+    p->device = dev;
+    p->nseg = nseg;
+    p->out_mode = out_dtype;
+    p->ntasks = (uint32_t)tasks.size();
+    p->nslots = slots;
+    p->blocks = xsum::segmented_blocks(cus, blocks_per_cu);
+    p->info.nseg = nseg;
+    p->info.lane_segments = lane_ids[0].size() + lane_ids[1].size() + lane_ids[2].size();
+    p->info.chunked_segments = chunk_ids.size();
+    p->info.chunks = nchunks_total;
+    p->info.work_items = tasks.size();
+    p->info.blocks = (uint32_t)p->blocks;
+    for (int d = 0; d < 3; ++d)
+        p->info.lane_max[d] = lane_max[d];
+    p->info.chunk_vectors = chunk_vectors;
+    p->info.workspace_bytes = xsum::kSegCtlBytes + (uint64_t)slots * sizeof(xsum_acc_t);
+
+    std::vector<xsum::SegTask> flat(tasks.size());
+    for (size_t i = 0; i < tasks.size(); ++i)
+        flat[i] = tasks[i].t;
+    hipError_t e = hipSuccess;
+    if (nseg)
+        e = hipMalloc((void **)&p->d_segs, nseg * sizeof(xsum::SegDesc));
+    if (e == hipSuccess && !flat.empty())
+        e = hipMalloc((void **)&p->d_tasks, flat.size() * sizeof(xsum::SegTask));
+    if (e == hipSuccess && !perm.empty())
+        e = hipMalloc((void **)&p->d_perm, perm.size() * sizeof(uint32_t));
+    if (e == hipSuccess && nseg)
+        e = hipMemcpy(p->d_segs, segs, nseg * sizeof(xsum::SegDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !flat.empty())
+        e = hipMemcpy(p->d_tasks, flat.data(), flat.size() * sizeof(xsum::SegTask),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !perm.empty())
+        e = hipMemcpy(p->d_perm, perm.data(), perm.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return e == hipErrorOutOfMemory ? api_fail(XSUM_ENOMEM, "plan allocation failed")
+                                        : api_hip_fail(e, "plan upload");
+    }
+    *plan_out = p;
+    return XSUM_OK;
+}
+
+void xsum_plan_destroy(xsum_plan_t *plan) { free_plan(plan); }
+
+xsum_status_t xsum_plan_get_info(const xsum_plan_t *plan, xsum_plan_info_t *info)
+{
+    if (plan == nullptr || info == nullptr)
+        return api_fail(XSUM_EINVAL, "plan or info is NULL");
+    *info = plan->info;
+    return XSUM_OK;
+}
+
+size_t xsum_segmented_workspace_size(const xsum_plan_t *plan)
+{
+    return plan ? (size_t)plan->info.workspace_bytes : 0;
+}
+
+xsum_status_t xsum_segmented_run(const xsum_plan_t *plan, const void *base,
+                                 void *out, uint32_t *flags, void *workspace,
+                                 size_t ws_bytes, void *stream)
+{
+    if (plan == nullptr)
+        return api_fail(XSUM_EINVAL, "plan is NULL");
+    if (plan->nseg == 0)
+        return XSUM_OK;
+    if (base == nullptr || out == nullptr || workspace == nullptr)
+        return api_fail(XSUM_EINVAL, "base, out or workspace is NULL");
+    if ((uintptr_t)base % 16 != 0)
+        return api_fail(XSUM_EINVAL, "base must be 16-byte aligned");
+    if ((uintptr_t)out % 8 != 0 || (uintptr_t)workspace % 8 != 0 ||
+        (flags && (uintptr_t)flags % 4 != 0))
+        return api_fail(XSUM_EINVAL, "misaligned out, flags or workspace");
+    if (ws_bytes < plan->info.workspace_bytes)
+        return api_fail(XSUM_EINVAL, "workspace smaller than xsum_segmented_workspace_size()");
+    int dev;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return api_hip_fail(e, "hipGetDevice");
+    if (dev != plan->device)
+        return api_fail(XSUM_EINVAL, "plan was built for another device");
+    uint8_t *ws = (uint8_t *)workspace;
+    e = xsum::launch_segmented(base, plan->d_segs, plan->d_tasks, plan->ntasks,
+                               plan->d_perm, (xsum_acc_t *)(ws + xsum::kSegCtlBytes),
+                               (xsum::SegCtl *)ws, plan->out_mode, (uint64_t *)out,
+                               flags, plan->blocks, (hipStream_t)stream);
+    return e == hipSuccess ? XSUM_OK : api_hip_fail(e, "kernel launch");
+}
+
+xsum_status_t xsum_segmented_workspace_init(void *workspace, size_t ws_bytes,
+                                            void *stream)
+{
+    if (ws_bytes == 0)
+        return XSUM_OK;
+    if (workspace == nullptr || (uintptr_t)workspace % 8 != 0 || ws_bytes % 8 != 0)
+        return api_fail(XSUM_EINVAL, "workspace NULL, misaligned or not a multiple of 8 bytes");
+    hipError_t e = xsum::launch_zero_words((uint64_t *)workspace, ws_bytes / 8,
+                                           (hipStream_t)stream);
+    return e == hipSuccess ? XSUM_OK : api_hip_fail(e, "kernel launch");
+}
+
+xsum_status_t xsum_segmented_capture(const xsum_plan_t *plan, const void *base,
+                                     void *out, uint32_t *flags,
+                                     void *workspace, size_t ws_bytes,
+                                     void **graph_exec)
+{
+    if (graph_exec == nullptr)
+        return api_fail(XSUM_EINVAL, "graph_exec is NULL");
+    *graph_exec = nullptr;
+    hipStream_t s;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return api_hip_fail(e, "hipStreamCreate");
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return api_hip_fail(e, "hipStreamBeginCapture");
+    }
+    xsum_status_t st = xsum_segmented_run(plan, base, out, flags, workspace, ws_bytes, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    (void)hipStreamDestroy(s);
+    if (st != XSUM_OK) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess)
+        return api_hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
+        return api_hip_fail(e, "hipGraphInstantiate");
+    *graph_exec = (void *)ex;
+    return XSUM_OK;
+}
+
+xsum_status_t xsum_graph_launch(void *graph_exec, void *stream)
+{
+    if (graph_exec == nullptr)
+        return api_fail(XSUM_EINVAL, "graph_exec is NULL");
+    hipError_t e = hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream);
+    return e == hipSuccess ? XSUM_OK : api_hip_fail(e, "hipGraphLaunch");
+}
+
+void xsum_graph_destroy(void *graph_exec)
+{
+    if (graph_exec)
+        (void)hipGraphExecDestroy((hipGraphExec_t)graph_exec);
+}
+
+}  // extern "C"

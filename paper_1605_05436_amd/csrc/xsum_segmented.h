@@ -1,0 +1,47 @@
+// Internal layout of a segmented-sum plan, shared by the planner (host) and
+// the segmented kernel (device).
+#pragma once
+
+#include <stdint.h>
+
+namespace xsum {
+
+// Copy of one caller descriptor (same layout as xsum_segment_t).
+struct SegDesc {
+    uint64_t byte_offset;
+    uint64_t length;
+    uint32_t dtype;
+    uint32_t reserved;
+};
+
+enum SegTaskKind : uint32_t {
+    kLaneGroup = 0,  // up to 64 whole segments, one per lane
+    kChunk = 1,      // one chunk of a long segment, summed by a whole wave
+};
+
+enum SegChunkFlags : uint32_t {
+    kChunkFirst = 1,  // also adds the segment's unaligned head elements
+    kChunkLast = 2,   // also adds the segment's ragged tail elements
+};
+
+// 32-byte work item.
+struct SegTask {
+    uint32_t kind_dtype_flags;  // kind | dtype << 8 | chunk flags << 16
+    uint32_t a;                 // lane group: first perm index; chunk: segment
+    uint32_t b;                 // lane group: lane count;       chunk: state slot
+    uint32_t nchunks;           // chunk: chunks of its segment
+    uint64_t v0;                // chunk: first 16-byte vector of the chunk
+    uint64_t nv;                // chunk: vectors in the chunk
+};
+
+// Control words at the start of the workspace.  Both return to zero at the
+// end of every launch (the last wave to finish resets them).
+struct SegCtl {
+    uint32_t head;   // next task to pop
+    uint32_t done;   // waves that found the queue empty
+    uint32_t pad[62];
+};
+
+static constexpr uint64_t kSegCtlBytes = sizeof(SegCtl);
+
+}  // namespace xsum

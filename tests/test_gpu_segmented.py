@@ -1,0 +1,151 @@
+"""GPU parity of segmented sums (xsum_segmented_plan / run / capture): every
+segment's result and flags equal the oracle's, for lane-group and chunked
+segments, all formats, any tuning, and across graph replays."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["f64", "f32", "bf16"]
+UINT = {0: np.uint64, 1: np.uint32, 2: np.uint16}
+SIZE = {0: 8, 1: 4, 2: 2}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1605_05436_amd  # noqa: F401
+    oracle.build_binned(force=False)
+
+
+def expected(buf, desc, out_fmt=None):
+    """Oracle (bits, flags) per segment."""
+    res = np.zeros(len(desc), dtype=np.uint64)
+    fl = np.zeros(len(desc), dtype=np.uint32)
+    for i, (off, length, dt, _) in enumerate(desc.tolist()):
+        seg = buf[off:off + length * SIZE[dt]].view(UINT[dt])
+        of = out_fmt if out_fmt else ("f64" if dt == 0 else "f32")
+        if length > 50_000:
+            b, f = oracle.oracle_sum_binned(seg, NAMES[dt], of, threads=4)
+        else:
+            b, f = oracle.oracle_sum(seg, NAMES[dt], of)
+        res[i], fl[i] = b, f
+    return res, fl
+
+
+def run_gpu(buf, desc, out_mode=None, tuning=None, repeats=1):
+    import torch
+    import paper_1605_05436_amd as xs
+    dbuf = torch.from_numpy(buf).to("cuda")
+    om = xs.SAME if out_mode is None else {"f64": 0, "f32": 1, "bf16": 2}[out_mode]
+    ss = xs.SegmentedSum(desc, om, tuning)
+    out = torch.zeros(len(desc), dtype=torch.int64, device="cuda")
+    fl = torch.zeros(len(desc), dtype=torch.int32, device="cuda")
+    results = []
+    for _ in range(repeats):
+        out.fill_(-1)
+        fl.fill_(-1)
+        ss.run(dbuf, out, fl)
+        torch.cuda.synchronize()
+        results.append((out.cpu().numpy().view(np.uint64).copy(),
+                        fl.cpu().numpy().view(np.uint32).copy()))
+    info = ss.info
+    ss.close()
+    return results, info
+
+
+def check(buf, desc, out_mode=None, tuning=None, repeats=1):
+    want = expected(buf, desc, out_mode)
+    results, info = run_gpu(buf, desc, out_mode, tuning, repeats)
+    for got in results:
+        bad = np.nonzero((got[0] != want[0]) | (got[1] != want[1]))[0]
+        assert bad.size == 0, ("mismatching segments", bad[:10].tolist(),
+                               desc[bad[:3]].tolist(), got[0][bad[:3]], want[0][bad[:3]])
+    return info
+
+
+def test_lognormal_batch_mixed_formats():
+    buf, desc = workloads.config4(nseg=20_000, seed=1)
+    info = check(buf, desc, repeats=2)
+    assert info["chunked_segments"] > 0 and info["lane_segments"] > 0
+
+
+def test_edge_segments():
+    rng = np.random.default_rng(3)
+    lengths = [0, 1, 2, 3, 7, 8, 9, 63, 64, 65, 4095, 4096, 4097, 8191, 8193,
+               16383, 16385, 100_000, 0, 1]
+    dtypes = [int(rng.integers(0, 3)) for _ in lengths]
+    buf, desc = workloads.config4(lengths=lengths, dtypes=dtypes, seed=4, kmin=-1000, kmax=1000,
+                                  align=16)
+    # misalign some starts by whole elements (offsets stay element-aligned)
+    shift = np.array([SIZE[d] * (i % 3) for i, d in enumerate(dtypes)], dtype=np.uint64)
+    nbuf = np.zeros(len(buf) + 64, dtype=np.uint8)
+    for i in range(len(desc)):
+        o, L, d = int(desc["byte_offset"][i]), int(desc["length"][i]), int(desc["dtype"][i])
+        no = o + int(shift[i])
+        nbuf[no:no + L * SIZE[d]] = buf[o:o + L * SIZE[d]]
+        desc["byte_offset"][i] = no
+    # specials in a few segments
+    for i, pat in ((5, None), (13, None), (17, None)):
+        o, d = int(desc["byte_offset"][i]), int(desc["dtype"][i])
+        if int(desc["length"][i]) > 2:
+            special = {0: 0x7FF0000000000000, 1: 0x7F800000, 2: 0x7F80}[d]
+            nbuf[o:o + SIZE[d]] = np.array([special], dtype=UINT[d]).view(np.uint8)
+    check(nbuf, desc)
+    for om in ("f64", "f32", "bf16"):
+        check(nbuf, desc, out_mode=om)
+
+
+@pytest.mark.parametrize("lane_max,chunk_vectors", [(1, 64), (100, 256), (1 << 20, 0),
+                                                    (0, 64 * 3 + 1)])
+def test_tuning_does_not_change_bits(lane_max, chunk_vectors):
+    import paper_1605_05436_amd as xs
+    buf, desc = workloads.config4(nseg=3000, seed=5, kmin=-300, kmax=300)
+    t = xs.SegTuning()
+    for d in range(3):
+        t.lane_max[d] = lane_max
+    t.chunk_vectors = chunk_vectors
+    info = check(buf, desc, tuning=t)
+    if lane_max == 1:
+        assert info["lane_segments"] <= int((desc["length"] <= 1).sum())
+
+
+def test_single_long_segment_equals_single_sum():
+    bits = workloads.family("mixed", 3_000_001, 2000, seed=9)
+    buf = bits.view(np.uint8)
+    desc = np.zeros(1, dtype=workloads.SEGMENT_DTYPE)
+    desc["length"] = len(bits)
+    check(buf, desc)
+
+
+def test_graph_replay_matches_eager():
+    import torch
+    import paper_1605_05436_amd as xs
+    buf, desc = workloads.config4(nseg=5000, seed=6)
+    want = expected(buf, desc)
+    dbuf = torch.from_numpy(buf).to("cuda")
+    ss = xs.SegmentedSum(desc)
+    out = torch.zeros(len(desc), dtype=torch.int64, device="cuda")
+    fl = torch.zeros(len(desc), dtype=torch.int32, device="cuda")
+    graph = ss.capture(dbuf, out, fl)
+    try:
+        for rep in range(4):
+            out.fill_(0)
+            fl.fill_(0)
+            xs.xsum_graph_launch(graph, xs.stream_handle())
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), want[0]), rep
+            assert np.array_equal(fl.cpu().numpy().view(np.uint32), want[1]), rep
+            # eager work between replays
+            ss.run(dbuf, out, fl)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), want[0])
+    finally:
+        xs.xsum_graph_destroy(graph)
+        ss.close()
