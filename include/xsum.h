@@ -179,25 +179,34 @@ typedef struct xsum_segment {
     uint32_t reserved;  /* ignored */
 } xsum_segment_t;
 
-/* Tuning knobs of a plan; 0 in any field means the library default.
- *   lane_max[d]   segments of dtype d with at most this many elements are
- *                 summed one per lane (default 4096 / 8192 / 16384 for
- *                 binary64 / binary32 / bfloat16); longer ones are split into
- *                 chunks summed by whole waves
- *   chunk_vectors 16-byte vectors per chunk (default 8192, range [64, 2^26])
+/* Tuning knobs of a plan, indexed by dtype d where per-format; 0 in any
+ * field means the library default.
+ *   lane_max[d]   segments with at most this many elements are summed one per
+ *                 lane, 64 to a wave (default 8192 / 16384 / 32768 for
+ *                 binary64 / binary32 / bfloat16)
+ *   wave_max[d]   longer segments with at most this many elements are summed
+ *                 whole by one wave (default: 4 MiB of input)
+ *   chunk_vectors longer segments still are cut into chunks of this many
+ *                 16-byte vectors, summed by separate waves whose states are
+ *                 merged (default 2^18 = 4 MiB, range [64, 2^26])
  *   blocks_per_cu resident one-wave workgroups per compute unit (default 4,
- *                 range [1, 16]) */
+ *                 range [1, 16])
+ *   lane_buckets  per-lane segments are grouped by length in this many
+ *                 buckets per doubling (default 4, at most 64) and taken in
+ *                 buffer order inside a bucket */
 typedef struct xsum_seg_tuning {
     uint64_t lane_max[3];
+    uint64_t wave_max[3];
     uint64_t chunk_vectors;
     uint32_t blocks_per_cu;
-    uint32_t reserved;
+    uint32_t lane_buckets;
 } xsum_seg_tuning_t;
 
 /* Plan statistics. */
 typedef struct xsum_plan_info {
-    uint64_t nseg, lane_segments, chunked_segments, chunks, work_items;
-    uint64_t lane_max[3], chunk_vectors, workspace_bytes;
+    uint64_t nseg, lane_segments, wave_segments, chunked_segments, chunks,
+        work_items;
+    uint64_t lane_max[3], wave_max[3], chunk_vectors, workspace_bytes;
     uint32_t blocks, reserved;
 } xsum_plan_info_t;
 
@@ -206,8 +215,9 @@ typedef struct xsum_plan xsum_plan_t;  /* opaque, owned by the library */
 /*
  * Build a plan from host descriptors (copied; the caller may free them).
  * Segments are bucketed by format and length: short ones are grouped 64 to a
- * wave, one per lane, longest first; long ones are cut into chunks, each with
- * a state slot in the workspace.  The plan lives on the current device.
+ * wave, one per lane, longest first; longer ones get a wave each; the longest
+ * are cut into chunks, each such segment with a state slot in the workspace.
+ * The plan lives on the current device.
  *   out_dtype  XSUM_SAME (binary64 for binary64 segments, binary32 for the
  *              others) or one output format for every segment
  *   tuning     may be NULL

@@ -38,15 +38,18 @@ EXPORTED = [
 
 class SegTuning(ctypes.Structure):
     """xsum_seg_tuning_t (0 = library default in every field)."""
-    _fields_ = [("lane_max", ctypes.c_uint64 * 3), ("chunk_vectors", ctypes.c_uint64),
-                ("blocks_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+    _fields_ = [("lane_max", ctypes.c_uint64 * 3), ("wave_max", ctypes.c_uint64 * 3),
+                ("chunk_vectors", ctypes.c_uint64),
+                ("blocks_per_cu", ctypes.c_uint32), ("lane_buckets", ctypes.c_uint32)]
 
 
 class PlanInfo(ctypes.Structure):
     """xsum_plan_info_t."""
     _fields_ = [("nseg", ctypes.c_uint64), ("lane_segments", ctypes.c_uint64),
+                ("wave_segments", ctypes.c_uint64),
                 ("chunked_segments", ctypes.c_uint64), ("chunks", ctypes.c_uint64),
                 ("work_items", ctypes.c_uint64), ("lane_max", ctypes.c_uint64 * 3),
+                ("wave_max", ctypes.c_uint64 * 3),
                 ("chunk_vectors", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
                 ("blocks", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
@@ -196,6 +199,7 @@ def xsum_plan_get_info(plan):
     _check(_lib.xsum_plan_get_info(_p(plan), ctypes.byref(info)))
     d = {k: getattr(info, k) for k, _ in PlanInfo._fields_ if k != "reserved"}
     d["lane_max"] = list(info.lane_max)
+    d["wave_max"] = list(info.wave_max)
     return d
 
 

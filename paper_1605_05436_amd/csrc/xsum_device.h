@@ -335,7 +335,7 @@ static constexpr uint32_t kIdentityFn = 0x24u;  // fields (0,1,2) -> (0,1,2)
 // 2l+1 (b); lane 33's b is the signed top digit; lanes above 33 hold zeros.
 // Inputs may be any int64 with |digit| < 2^62.  On return digits 0..66 are in
 // [0, 2^32) and the top digit holds the rest, so the value is unchanged.
-static __device__ void normalise_wave(int64_t &a, int64_t &b, int lane)
+static __device__ __forceinline__ void normalise_wave(int64_t &a, int64_t &b, int lane)
 {
     const bool top_lane = lane == 33;
     const bool live = lane <= 33;
@@ -407,7 +407,7 @@ __device__ __forceinline__ uint64_t fmt_qnan(const OutFormat &f)
 // Round-to-nearest-even of the magnitude whose top non-zero digit is h
 // (value w2), with the next two digits w1, w0 (zero below digit 0) and a
 // sticky flag for any non-zero digit below h-2.
-static __device__ uint64_t round_magnitude(bool neg, int h, uint32_t w2, uint32_t w1,
+static __device__ __forceinline__ uint64_t round_magnitude(bool neg, int h, uint32_t w2, uint32_t w1,
                                     uint32_t w0, bool sticky_below,
                                     const OutFormat &f, uint32_t &flags)
 {
@@ -479,7 +479,7 @@ __device__ __forceinline__ bool special_result(uint32_t special,
     return false;
 }
 
-static __device__ uint64_t round_wave(int64_t a, int64_t b, int lane,
+static __device__ __forceinline__ uint64_t round_wave(int64_t a, int64_t b, int lane,
                                uint32_t special, int out_fmt, uint32_t &flags)
 {
     const OutFormat f = out_format(out_fmt);
@@ -602,13 +602,81 @@ struct LaneFinisher {
             flags = XSUM_FLAG_OVERFLOW | XSUM_FLAG_INEXACT;
             return fmt_inf(f, negative);
         }
-        const TopTracker &t = negative ? neg : pos;
-        if (t.h < 0)
+        // select by value (a reference chosen at run time would force both
+        // trackers into memory)
+        const int h = negative ? neg.h : pos.h;
+        if (h < 0)
             return 0;                                // exact zero -> +0
-        return round_magnitude(negative, digit0 + t.h, t.w2, t.w1, t.w0,
-                               t.sticky, f, flags);
+        const uint32_t w2 = negative ? neg.w2 : pos.w2;
+        const uint32_t w1 = negative ? neg.w1 : pos.w1;
+        const uint32_t w0 = negative ? neg.w0 : pos.w0;
+        const bool sticky = negative ? neg.sticky : pos.sticky;
+        return round_magnitude(negative, digit0 + h, w2, w1, w0, sticky, f,
+                               flags);
     }
 };
+
+// Two-pass rounding of one lane's digits (digit d of the lane is at
+// col[d * 64], weight 2^(32 (digit0 + d)) in units of 2^-1074), used when a
+// lane owns a whole segment.  Pass 1 carries the N raw digits upward and
+// writes the canonical digits back, noting the lowest non-zero digit z, the
+// highest non-zero digit and the highest digit that is not all ones; the
+// final carry is the sign.  Pass 2 reads the three digits the rounding needs:
+// for a negative sum the magnitude's digits are 0 below z, 2^32 - u at z and
+// 2^32 - 1 - u above it, so in both cases "any non-zero digit below h - 2"
+// is simply z < h - 2.  The N entries are zeroed afterwards.
+template <int N>
+__device__ __forceinline__ uint64_t finish_lane_digits(uint64_t *col,
+                                                       int digit0,
+                                                       uint32_t special,
+                                                       int out_fmt,
+                                                       uint32_t &flags)
+{
+    int64_t carry = 0;
+    int z = -1, hnz = -1, hff = -1;
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+        const int64_t x = (int64_t)lds_load(col + d * 64) + carry;
+        const uint32_t u = (uint32_t)((uint64_t)x & kLow32);
+        carry = x >> 32;
+        lds_store(col + d * 64, u);
+        if (u != 0) {
+            hnz = d;
+            z = (z < 0) ? d : z;
+        }
+        if (u != 0xffffffffu)
+            hff = d;
+    }
+    const OutFormat f = out_format(out_fmt);
+    flags = 0;
+    uint64_t bits;
+    const bool negative = carry < 0;
+    if (special_result(special, f, bits, flags)) {
+    } else if (!(carry == 0 || carry == -1) || (negative && z < 0)) {
+        // beyond the digits: far above every format's range
+        flags = XSUM_FLAG_OVERFLOW | XSUM_FLAG_INEXACT;
+        bits = fmt_inf(f, negative);
+    } else if (!negative && hnz < 0) {
+        bits = 0;                                   // exact zero -> +0
+    } else {
+        const int h = negative ? (hff > z ? hff : z) : hnz;
+        uint32_t w[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int d = h - i;
+            uint32_t u = d >= 0 ? (uint32_t)lds_load(col + (d >= 0 ? d : 0) * 64) : 0u;
+            if (negative)
+                u = d < z ? 0u : (d == z ? 0u - u : ~u);
+            w[i] = u;
+        }
+        bits = round_magnitude(negative, digit0 + h, w[0], w[1], w[2], z < h - 2,
+                               f, flags);
+    }
+#pragma unroll
+    for (int d = 0; d < N; ++d)
+        lds_store(col + d * 64, 0);
+    return bits;
+}
 
 __device__ __forceinline__ void store_result(void *out, int out_fmt,
                                              uint64_t bits)
@@ -632,7 +700,7 @@ __device__ __forceinline__ void gstore(int64_t *p, int64_t v)
 }
 
 // Last-block work of an accumulation launch, run by one full wave.
-static __device__ void finish_state(xsum_acc_t *acc, const Finish &fin, int lane)
+static __device__ __forceinline__ void finish_state(xsum_acc_t *acc, const Finish &fin, int lane)
 {
     int64_t a = 0, b = 0;
     const bool live = lane <= 33;

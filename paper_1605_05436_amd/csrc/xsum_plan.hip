@@ -46,8 +46,10 @@ using xsum::api_hip_fail;
 constexpr int kPerVec[3] = {2, 4, 8};
 constexpr int kBytes[3] = {8, 4, 2};
 // Default per-lane limits: segments up to this many elements are summed one
-// per lane (32 KiB of input per lane).
-constexpr uint64_t kLaneMaxDefault[3] = {4096, 8192, 16384};
+// per lane (64 KiB of input per lane).
+constexpr uint64_t kLaneMaxDefault[3] = {8192, 16384, 32768};
+// Segments up to 4 MiB are summed whole by one wave.
+constexpr uint64_t kWaveMaxDefault[3] = {1ull << 19, 1ull << 20, 1ull << 21};
 
 void free_plan(xsum_plan *p)
 {
@@ -80,15 +82,25 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
     if (!(out_dtype == XSUM_SAME || out_dtype == XSUM_F64 || out_dtype == XSUM_F32 ||
           out_dtype == XSUM_BF16))
         return api_fail(XSUM_EDTYPE, "unknown output dtype " + std::to_string(out_dtype));
-    uint64_t lane_max[3];
-    for (int d = 0; d < 3; ++d)
+    uint64_t lane_max[3], wave_max[3];
+    for (int d = 0; d < 3; ++d) {
         lane_max[d] = kLaneMaxDefault[d];
+        wave_max[d] = kWaveMaxDefault[d];
+    }
     uint64_t chunk_vectors = xsum::segmented_chunk_vectors();
     int blocks_per_cu = 0;
+    int lane_buckets = 4;
     if (tuning) {
-        for (int d = 0; d < 3; ++d)
+        if (tuning->lane_buckets)
+            lane_buckets = (int)tuning->lane_buckets;
+        if (lane_buckets > 64)
+            return api_fail(XSUM_ERANGE, "lane_buckets above 64");
+        for (int d = 0; d < 3; ++d) {
             if (tuning->lane_max[d])
                 lane_max[d] = tuning->lane_max[d];
+            if (tuning->wave_max[d])
+                wave_max[d] = tuning->wave_max[d];
+        }
         if (tuning->chunk_vectors)
             chunk_vectors = tuning->chunk_vectors;
         blocks_per_cu = (int)tuning->blocks_per_cu;
@@ -99,8 +111,9 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
         if (blocks_per_cu < 0 || blocks_per_cu > 16)
             return api_fail(XSUM_ERANGE, "blocks_per_cu out of range [0, 16]");
     }
-    // validate descriptors, split into per-lane and chunked segments
+    // validate descriptors, split into per-lane, per-wave and chunked segments
     std::vector<uint32_t> lane_ids[3];
+    std::vector<uint32_t> wave_ids;
     std::vector<uint32_t> chunk_ids;
     for (uint64_t i = 0; i < nseg; ++i) {
         const uint32_t dt = segs[i].dtype;
@@ -113,6 +126,8 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
             return api_fail(XSUM_ERANGE, "segment " + std::to_string(i) + ": length above 2^40");
         if (segs[i].length <= lane_max[dt])
             lane_ids[dt].push_back((uint32_t)i);
+        else if (segs[i].length <= wave_max[dt])
+            wave_ids.push_back((uint32_t)i);
         else
             chunk_ids.push_back((uint32_t)i);
     }
@@ -152,11 +167,37 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
         nchunks_total += nch;
         ++slots;
     }
-    // short segments: sorted by length (longest first), 64 per lane group
+    // longer segments: one wave each
+    for (uint32_t id : wave_ids) {
+        const uint32_t dt = segs[id].dtype;
+        HostTask h{};
+        h.t.kind_dtype_flags = xsum::kWhole | (dt << 8);
+        h.t.a = id;
+        h.cost = segs[id].length / kPerVec[dt] / 64 + 1;
+        tasks.push_back(h);
+    }
+    // short segments, 64 per lane group: bucketed by length (lane_buckets
+    // buckets per doubling, longest bucket first) so a group's lanes finish
+    // together, and in buffer order inside a bucket so a group's 64 streams
+    // stay close in memory (few distinct pages per load instruction)
     for (int dt = 0; dt < 3; ++dt) {
         std::vector<uint32_t> &ids = lane_ids[dt];
+        auto bucket = [&](uint32_t id) -> int {
+            const uint64_t L = segs[id].length;
+            if (L == 0)
+                return -1;
+            int b = 63 - __builtin_clzll(L);          // floor(log2 L)
+            if (lane_buckets <= 1)
+                return b;
+            // fractional part of log2 L from the bits below the leading one
+            const uint64_t frac = b >= 8 ? (L >> (b - 8)) & 0xff : (L << (8 - b)) & 0xff;
+            return b * lane_buckets + (int)((frac * (uint64_t)lane_buckets) >> 8);
+        };
         std::stable_sort(ids.begin(), ids.end(), [&](uint32_t x, uint32_t y) {
-            return segs[x].length > segs[y].length;
+            const int bx = bucket(x), by = bucket(y);
+            if (bx != by)
+                return bx > by;
+            return segs[x].byte_offset < segs[y].byte_offset;
         });
         for (size_t g = 0; g < ids.size(); g += 64) {
             const size_t cnt = std::min<size_t>(64, ids.size() - g);
@@ -164,7 +205,10 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
             h.t.kind_dtype_flags = xsum::kLaneGroup | ((uint32_t)dt << 8);
             h.t.a = (uint32_t)perm.size();
             h.t.b = (uint32_t)cnt;
-            h.cost = segs[ids[g]].length / kPerVec[dt] + 1;
+            uint64_t maxlen = 0;
+            for (size_t k = g; k < g + cnt; ++k)
+                maxlen = std::max<uint64_t>(maxlen, segs[ids[k]].length);
+            h.cost = maxlen / kPerVec[dt] + 1;
             tasks.push_back(h);
             perm.insert(perm.end(), ids.begin() + g, ids.begin() + g + cnt);
         }
@@ -188,12 +232,15 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
     p->blocks = xsum::segmented_blocks(cus, blocks_per_cu);
     p->info.nseg = nseg;
     p->info.lane_segments = lane_ids[0].size() + lane_ids[1].size() + lane_ids[2].size();
+    p->info.wave_segments = wave_ids.size();
     p->info.chunked_segments = chunk_ids.size();
     p->info.chunks = nchunks_total;
     p->info.work_items = tasks.size();
     p->info.blocks = (uint32_t)p->blocks;
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d) {
         p->info.lane_max[d] = lane_max[d];
+        p->info.wave_max[d] = wave_max[d];
+    }
     p->info.chunk_vectors = chunk_vectors;
     p->info.workspace_bytes = xsum::kSegCtlBytes + (uint64_t)slots * sizeof(xsum_acc_t);
 

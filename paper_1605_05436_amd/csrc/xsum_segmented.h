@@ -16,7 +16,8 @@ struct SegDesc {
 
 enum SegTaskKind : uint32_t {
     kLaneGroup = 0,  // up to 64 whole segments, one per lane
-    kChunk = 1,      // one chunk of a long segment, summed by a whole wave
+    kChunk = 1,      // one chunk of a very long segment, summed by a wave
+    kWhole = 2,      // one whole segment, summed and rounded by one wave
 };
 
 enum SegChunkFlags : uint32_t {
@@ -27,8 +28,8 @@ enum SegChunkFlags : uint32_t {
 // 32-byte work item.
 struct SegTask {
     uint32_t kind_dtype_flags;  // kind | dtype << 8 | chunk flags << 16
-    uint32_t a;                 // lane group: first perm index; chunk: segment
-    uint32_t b;                 // lane group: lane count;       chunk: state slot
+    uint32_t a;                 // lane group: first perm index; else: segment
+    uint32_t b;                 // lane group: lane count;  chunk: state slot
     uint32_t nchunks;           // chunk: chunks of its segment
     uint64_t v0;                // chunk: first 16-byte vector of the chunk
     uint64_t nv;                // chunk: vectors in the chunk

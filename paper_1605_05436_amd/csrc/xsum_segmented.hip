@@ -10,10 +10,15 @@
 //     into its private LDS column exactly as the single-sum kernel does, then
 //     carry-normalises and rounds it alone (LaneFinisher), so a segment costs
 //     about 1/64 of a wave's fixed work.
-//   * chunk: a contiguous run of one long segment, loaded coalesced by a whole
+//   * whole segment: a longer segment loaded coalesced by one wave, which
+//     merges its 64 columns, carry-normalises and rounds with no state in
+//     global memory and no device-scope fence.
+//   * chunk: a contiguous run of a very long segment, loaded coalesced by a
 //     wave.  The wave merges its 64 columns and adds the digits into the
 //     segment's state with int64 atomics; a per-segment ticket lets the last
-//     chunk round the state (and zero it for the next launch).
+//     chunk round the state (and zero it for the next launch).  The ticket
+//     needs device-scope fences, which on this part write back and invalidate
+//     L2, so chunks are large and rare.
 // The queue head and the exit counter return to zero at the end of every
 // launch, so a launch can be replayed from a captured graph without memsets.
 #include <hip/hip_runtime.h>
@@ -72,46 +77,55 @@ __device__ __forceinline__ uint32_t wave_or_u32(uint32_t v)
 
 // Round the lane's own column and zero it.  binary64 columns are digits
 // 0..65; binary32 bins (weight 2^(8(b + 115))) are first moved to radix-2^32
-// digits 28..38 (each bin split into 32-bit halves so no shift overflows).
+// digits 28..39, written back over the bins they came from (digit 28 + i
+// lands in entry i, never past a bin still to be read), each bin split into
+// 32-bit halves so no shift overflows; two top digits take any carry.
 template <int FMT>
 __device__ __forceinline__ uint64_t finish_lane(uint64_t *col, uint32_t spec,
                                                 int out_fmt, uint32_t &flags)
 {
-    LaneFinisher fin;
     if constexpr (FMT == XSUM_F64) {
-#pragma unroll
-        for (int d = 0; d < Geo<XSUM_F64>::kN; ++d) {
-            fin.feed((int64_t)lds_load(col + d * 64));
-            lds_store(col + d * 64, 0);
-        }
-        return fin.round(spec, out_fmt, 0, flags);
+        return finish_lane_digits<Geo<XSUM_F64>::kN>(col, 0, spec, out_fmt, flags);
     } else {
-        constexpr int kD = 11;           // digits 28..38
-        int64_t dig[kD];
-#pragma unroll
-        for (int i = 0; i < kD; ++i)
-            dig[i] = 0;
+        constexpr int kBin0 = Geo<FMT>::kBin0;
+        constexpr int kDigit0 = kBin0 >> 2;        // 28
+        int64_t cur = 0, nxt = 0;                  // digits g and g + 1
+        int g_prev = kDigit0;
 #pragma unroll
         for (int b = 0; b < Geo<FMT>::kN; ++b) {
+            const int g = (b + kBin0) >> 2;
+            const int sh = 8 * ((b + kBin0) & 3);
             const int64_t v = (int64_t)lds_load(col + b * 64);
-            lds_store(col + b * 64, 0);
-            const int g = ((b + Geo<FMT>::kBin0) >> 2) - 28;
-            const int sh = 8 * ((b + Geo<FMT>::kBin0) & 3);
+            if (g != g_prev) {
+                lds_store(col + (g_prev - kDigit0) * 64, (uint64_t)cur);
+                cur = nxt;
+                nxt = 0;
+                g_prev = g;
+            }
             const uint64_t lo = ((uint64_t)v & kLow32) << sh;     // < 2^56
             const int64_t hi = (int64_t)((uint64_t)(v >> 32) << sh);
-            dig[g] += (int64_t)(lo & kLow32);
-            dig[g + 1] += (int64_t)(lo >> 32) + hi;
+            cur += (int64_t)(lo & kLow32);
+            nxt += (int64_t)(lo >> 32) + hi;
         }
+        // digits 36 and 37, then two empty digits for the carry
+        constexpr int kLast = (Geo<FMT>::kN - 1 + kBin0) >> 2;   // 36
+        lds_store(col + (kLast - kDigit0) * 64, (uint64_t)cur);
+        lds_store(col + (kLast + 1 - kDigit0) * 64, (uint64_t)nxt);
+        lds_store(col + (kLast + 2 - kDigit0) * 64, 0);
+        lds_store(col + (kLast + 3 - kDigit0) * 64, 0);
+        const uint64_t bits = finish_lane_digits<kLast + 4 - kDigit0>(col, kDigit0, spec,
+                                                                      out_fmt, flags);
+        // bins above the digits (entries 12..32) were left as they were
 #pragma unroll
-        for (int i = 0; i < kD; ++i)
-            fin.feed(dig[i]);
-        return fin.round(spec, out_fmt, 28, flags);
+        for (int b = kLast + 4 - kDigit0; b < Geo<FMT>::kN; ++b)
+            lds_store(col + b * 64, 0);
+        return bits;
     }
 }
 
 // One lane group: lane l < count sums segment perm[first + l].
 template <int FMT, int UL>
-__device__ void run_lane_group(const uint8_t *base, const SegDesc *segs,
+__device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegDesc *segs,
                                const uint32_t *perm, uint32_t first,
                                uint32_t count, uint64_t *col, int out_mode,
                                uint64_t *out, uint32_t *flags, int lane)
@@ -136,24 +150,42 @@ __device__ void run_lane_group(const uint8_t *base, const SegDesc *segs,
 
     const uint64_t my_iters = (nv + UL - 1) / UL;
     const uint32_t iters = wave_max_u32((uint32_t)my_iters);
-    constexpr int kNormIters = 512 / UL;   // binary64: <= 1024 + 2*UL + 14 elements between normalisations
+    // binary64: at most 1024 + 2*UL + 2 elements between normalisations
+    constexpr int kNormIters = 512 / UL;
     int since = 0;
-    for (uint32_t it = 0; it < iters; ++it) {
-        vec4u q[UL];
+    // each lane walks its own segment, UL vectors per step, the next step's
+    // loads in flight while the current step is added
+    vec4u qa[UL], qb[UL];
+    auto load_step = [&](vec4u (&q)[UL], uint32_t it) {
 #pragma unroll
         for (int j = 0; j < UL; ++j) {
             const uint64_t i = (uint64_t)it * UL + j;
             q[j] = vec4u{0u, 0u, 0u, 0u};
             if (i < nv)
-                q[j] = __builtin_nontemporal_load(vp + i);
+                q[j] = vp[i];   // cached: a lane's UL loads share its lines
         }
-        add_tile<FMT, UL>(q, col, spec);
+    };
+    auto norm_step = [&]() {
         if constexpr (FMT == XSUM_F64) {
             if (++since >= kNormIters) {
                 normalise_column<G::kN>(col);
                 since = 0;
             }
         }
+    };
+    if (iters > 0)
+        load_step(qa, 0);
+    for (uint32_t it = 0; it < iters; it += 2) {
+        if (it + 1 < iters)
+            load_step(qb, it + 1);
+        add_tile<FMT, UL>(qa, col, spec);
+        norm_step();
+        if (it + 1 >= iters)
+            break;
+        if (it + 2 < iters)
+            load_step(qa, it + 2);
+        add_tile<FMT, UL>(qb, col, spec);
+        norm_step();
     }
     for (uint64_t i = 0; i < head; ++i)
         add_scalar<FMT>(p + i * G::kBytes, col, spec);
@@ -171,28 +203,18 @@ __device__ void run_lane_group(const uint8_t *base, const SegDesc *segs,
     }
 }
 
-// One chunk of a long segment, summed by the whole wave.
+// Add nv 16-byte vectors starting at vp (wave-contiguous tiles of 64*UC
+// vectors, the next tile in flight), plus the segment's head and tail
+// elements when asked, into the lanes' columns.
 template <int FMT, int UC>
-__device__ void run_chunk(const uint8_t *base, const SegDesc *segs,
-                          const SegTask &t, xsum_acc_t *states, WaveLds &w,
-                          uint64_t *col, int out_mode, uint64_t *out,
-                          uint32_t *flags, int lane)
+__device__ __forceinline__ void accumulate_span(const vec4u *vp, uint64_t nv,
+                                                const uint8_t *head_p,
+                                                uint64_t head,
+                                                const uint8_t *tail_p,
+                                                uint64_t tail, uint64_t *col,
+                                                uint32_t &spec, int lane)
 {
     using G = Geo<FMT>;
-    const uint32_t s = t.a;
-    const uint32_t cflags = t.kind_dtype_flags >> 16;
-    const uint8_t *p = base + segs[s].byte_offset;
-    const uint64_t L = segs[s].length;
-    uint64_t head = ((16 - ((uintptr_t)p & 15)) & 15) / G::kBytes;
-    if (head > L)
-        head = L;
-    const uint64_t nvs = (L - head) / G::kPerVec;
-    const uint64_t tail = L - head - nvs * G::kPerVec;
-    const vec4u *vp = (const vec4u *)(p + head * G::kBytes) + t.v0;
-    const uint64_t nv = t.nv;
-    uint32_t spec = 0;
-
-    // wave-contiguous tiles of 64*UC vectors, next tile in flight
     constexpr uint64_t kTile = 64ull * UC;
     constexpr int kNormTiles = 512 / UC;
     const uint64_t full = nv / kTile;
@@ -228,23 +250,106 @@ __device__ void run_chunk(const uint8_t *base, const SegDesc *segs,
             }
         }
     }
-    for (uint64_t i = full * kTile + lane; i < nv; i += 64) {
-        vec4u q[1] = {__builtin_nontemporal_load(vp + i)};
-        add_tile<FMT, 1>(q, col, spec);
+    // the last partial tile: all its loads issued before any is consumed
+    {
+        vec4u q[UC];
+#pragma unroll
+        for (int j = 0; j < UC; ++j) {
+            const uint64_t i = full * kTile + (uint64_t)j * 64 + lane;
+            q[j] = vec4u{0u, 0u, 0u, 0u};
+            if (i < nv)
+                q[j] = __builtin_nontemporal_load(vp + i);
+        }
+        add_tile<FMT, UC>(q, col, spec);
     }
-    if ((cflags & kChunkFirst) && (uint64_t)lane < head)
-        add_scalar<FMT>(p + (uint64_t)lane * G::kBytes, col, spec);
-    if ((cflags & kChunkLast) && (uint64_t)lane < tail)
-        add_scalar<FMT>(p + head * G::kBytes + nvs * 16 + (uint64_t)lane * G::kBytes,
-                        col, spec);
+    if ((uint64_t)lane < head)
+        add_scalar<FMT>(head_p + (uint64_t)lane * G::kBytes, col, spec);
+    if ((uint64_t)lane < tail)
+        add_scalar<FMT>(tail_p + (uint64_t)lane * G::kBytes, col, spec);
+}
 
-    // merge the wave's columns, then clear them for the next item
+// Merge the wave's 64 columns into w.merged, then clear the columns.
+template <int FMT>
+__device__ __forceinline__ void merge_and_clear(WaveLds &w, uint64_t *col,
+                                                int lane)
+{
     for (int d = lane; d < kDigits; d += 64)
         w.merged[d] = 0;
     wave_lds_fence();
     merge_wave_columns<FMT>(w.cols, w.merged, lane);
     wave_lds_fence();
     zero_column<FMT>(col);
+}
+
+struct SpanGeom {
+    const uint8_t *p;
+    uint64_t head, nvs, tail;
+};
+
+template <int FMT>
+__device__ __forceinline__ SpanGeom span_geom(const uint8_t *base,
+                                              const SegDesc &d)
+{
+    using G = Geo<FMT>;
+    SpanGeom g;
+    g.p = base + d.byte_offset;
+    const uint64_t L = d.length;
+    g.head = ((16 - ((uintptr_t)g.p & 15)) & 15) / G::kBytes;
+    if (g.head > L)
+        g.head = L;
+    g.nvs = (L - g.head) / G::kPerVec;
+    g.tail = L - g.head - g.nvs * G::kPerVec;
+    return g;
+}
+
+// One whole segment, summed, normalised and rounded by one wave.
+template <int FMT, int UC>
+__device__ __forceinline__ void run_whole(const uint8_t *base, const SegDesc *segs, uint32_t s,
+                          WaveLds &w, uint64_t *col, int out_mode,
+                          uint64_t *out, uint32_t *flags, int lane)
+{
+    using G = Geo<FMT>;
+    const SpanGeom g = span_geom<FMT>(base, segs[s]);
+    const vec4u *vp = (const vec4u *)(g.p + g.head * G::kBytes);
+    uint32_t spec = 0;
+    accumulate_span<FMT, UC>(vp, g.nvs, g.p, g.head,
+                             g.p + g.head * G::kBytes + g.nvs * 16, g.tail, col,
+                             spec, lane);
+    merge_and_clear<FMT>(w, col, lane);
+    spec = wave_or_u32(spec);
+    int64_t a = 0, b = 0;
+    if (lane <= 33) {
+        a = w.merged[2 * lane];
+        b = w.merged[2 * lane + 1];
+    }
+    normalise_wave(a, b, lane);
+    const int of = out_mode == XSUM_SAME ? LaneOut<FMT>::kNatural : out_mode;
+    uint32_t fl;
+    const uint64_t bits = round_wave(a, b, lane, spec, of, fl);
+    if (lane == 0) {
+        out[s] = bits;
+        if (flags)
+            flags[s] = fl;
+    }
+}
+
+// One chunk of a very long segment, summed by the whole wave.
+template <int FMT, int UC>
+__device__ __forceinline__ void run_chunk(const uint8_t *base, const SegDesc *segs,
+                          const SegTask &t, xsum_acc_t *states, WaveLds &w,
+                          uint64_t *col, int out_mode, uint64_t *out,
+                          uint32_t *flags, int lane)
+{
+    using G = Geo<FMT>;
+    const uint32_t s = t.a;
+    const uint32_t cflags = t.kind_dtype_flags >> 16;
+    const SpanGeom g = span_geom<FMT>(base, segs[s]);
+    const vec4u *vp = (const vec4u *)(g.p + g.head * G::kBytes) + t.v0;
+    uint32_t spec = 0;
+    accumulate_span<FMT, UC>(vp, t.nv, g.p, (cflags & kChunkFirst) ? g.head : 0,
+                             g.p + g.head * G::kBytes + g.nvs * 16,
+                             (cflags & kChunkLast) ? g.tail : 0, col, spec, lane);
+    merge_and_clear<FMT>(w, col, lane);
     spec = wave_or_u32(spec);
 
     xsum_acc_t *st = &states[t.b];
@@ -281,14 +386,27 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
     uint64_t *col = &w.cols[0][lane];
     zero_column<XSUM_F64>(col);
 
-    for (;;) {
-        uint32_t ti = 0;
+    // the next item is popped as soon as the current one is known, so the
+    // atomic's round trip overlaps with the current item's work
+    uint32_t cur = 0, next = 0;
+    if (lane == 0) {
+        cur = atomicAdd(&ctl->head, 1u);
+        next = atomicAdd(&ctl->head, 1u);
+    }
+    cur = __shfl(cur, 0, 64);
+    SegTask t{};
+    if (cur < ntasks)
+        t = tasks[cur];
+    next = __shfl(next, 0, 64);
+    while (cur < ntasks) {
+        // the record of the following item is fetched and the item after it
+        // popped while this one runs
+        SegTask nt{};
+        if (next < ntasks)
+            nt = tasks[next];
+        uint32_t nn = 0;
         if (lane == 0)
-            ti = atomicAdd(&ctl->head, 1u);
-        ti = __shfl(ti, 0, 64);
-        if (ti >= ntasks)
-            break;
-        const SegTask t = tasks[ti];
+            nn = atomicAdd(&ctl->head, 1u);
         const uint32_t kind = t.kind_dtype_flags & 0xffu;
         const uint32_t dtype = (t.kind_dtype_flags >> 8) & 0xffu;
         if (kind == kLaneGroup) {
@@ -298,6 +416,13 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
                 run_lane_group<XSUM_F32, UL>(base, segs, perm, t.a, t.b, col, out_mode, out, flags, lane);
             else
                 run_lane_group<XSUM_BF16, UL>(base, segs, perm, t.a, t.b, col, out_mode, out, flags, lane);
+        } else if (kind == kWhole) {
+            if (dtype == XSUM_F64)
+                run_whole<XSUM_F64, UC>(base, segs, t.a, w, col, out_mode, out, flags, lane);
+            else if (dtype == XSUM_F32)
+                run_whole<XSUM_F32, UC>(base, segs, t.a, w, col, out_mode, out, flags, lane);
+            else
+                run_whole<XSUM_BF16, UC>(base, segs, t.a, w, col, out_mode, out, flags, lane);
         } else {
             if (dtype == XSUM_F64)
                 run_chunk<XSUM_F64, UC>(base, segs, t, states, w, col, out_mode, out, flags, lane);
@@ -306,10 +431,14 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
             else
                 run_chunk<XSUM_BF16, UC>(base, segs, t, states, w, col, out_mode, out, flags, lane);
         }
+        cur = next;
+        t = nt;
+        next = __shfl(nn, 0, 64);
     }
-    // the last wave out resets the queue for the next launch
+    // The last wave out resets the queue for the next launch.  Every wave's
+    // final pop returned before its exit increment was issued, so no fence
+    // is needed here.
     if (lane == 0) {
-        __threadfence();
         const uint32_t total = gridDim.x * WAVES;
         if (atomicAdd(&ctl->done, 1u) == total - 1) {
             __hip_atomic_store(&ctl->head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -319,7 +448,7 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
 }
 
 static constexpr int kSegWaves = 1;
-static constexpr int kSegLaneUnroll = 4;
+static constexpr int kSegLaneUnroll = 16;
 static constexpr int kSegChunkUnroll = 16;
 static constexpr int kSegBlocksPerCu = 4;
 
@@ -341,6 +470,6 @@ hipError_t launch_segmented(const void *base, const SegDesc *segs,
     return hipGetLastError();
 }
 
-uint64_t segmented_chunk_vectors() { return 64ull * kSegChunkUnroll * 8; }
+uint64_t segmented_chunk_vectors() { return 1ull << 18; }  // 4 MiB
 
 }  // namespace xsum

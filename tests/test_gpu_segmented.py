@@ -1,6 +1,6 @@
 """GPU parity of segmented sums (xsum_segmented_plan / run / capture): every
-segment's result and flags equal the oracle's, for lane-group and chunked
-segments, all formats, any tuning, and across graph replays."""
+segment's result and flags equal the oracle's, for lane-group, whole-wave and
+chunked segments, all formats, any tuning, and across graph replays."""
 
 import numpy as np
 import pytest
@@ -73,7 +73,7 @@ def check(buf, desc, out_mode=None, tuning=None, repeats=1):
 def test_lognormal_batch_mixed_formats():
     buf, desc = workloads.config4(nseg=20_000, seed=1)
     info = check(buf, desc, repeats=2)
-    assert info["chunked_segments"] > 0 and info["lane_segments"] > 0
+    assert info["wave_segments"] > 0 and info["lane_segments"] > 0
 
 
 def test_edge_segments():
@@ -102,18 +102,24 @@ def test_edge_segments():
         check(nbuf, desc, out_mode=om)
 
 
-@pytest.mark.parametrize("lane_max,chunk_vectors", [(1, 64), (100, 256), (1 << 20, 0),
-                                                    (0, 64 * 3 + 1)])
-def test_tuning_does_not_change_bits(lane_max, chunk_vectors):
+@pytest.mark.parametrize("lane_max,wave_max,chunk_vectors",
+                         [(1, 1, 64), (100, 1000, 256), (1 << 20, 0, 0), (0, 0, 64 * 3 + 1),
+                          (1, 1 << 40, 0), (50, 5000, 64 * 5 + 7)])
+def test_tuning_does_not_change_bits(lane_max, wave_max, chunk_vectors):
     import paper_1605_05436_amd as xs
     buf, desc = workloads.config4(nseg=3000, seed=5, kmin=-300, kmax=300)
     t = xs.SegTuning()
     for d in range(3):
         t.lane_max[d] = lane_max
+        t.wave_max[d] = wave_max
     t.chunk_vectors = chunk_vectors
     info = check(buf, desc, tuning=t)
     if lane_max == 1:
         assert info["lane_segments"] <= int((desc["length"] <= 1).sum())
+    if wave_max == 1:
+        assert info["wave_segments"] == 0 and info["chunked_segments"] > 0
+    if wave_max == 1 << 40:
+        assert info["chunked_segments"] == 0 and info["wave_segments"] > 0
 
 
 def test_single_long_segment_equals_single_sum():

@@ -277,12 +277,21 @@ def config4(nseg=1_000_000, seed=0, lengths=None, dtypes=None, kmin=-50,
     names = [F64, F32, BF16]
 
     def work(ci):
+        # values of one chunk of 4096 segments are drawn per format in bulk,
+        # then cut into the chunk's segments in order
         rng = np.random.default_rng(children[ci])
-        for s in range(ci * 4096, min(nseg, (ci + 1) * 4096)):
-            f = names[D[s]]
-            v = uniform_values(rng, int(L[s]), f, kmin, kmax).astype(UINT[f])
+        lo, hi = ci * 4096, min(nseg, (ci + 1) * 4096)
+        pools, taken = [], [0, 0, 0]
+        for d in range(3):
+            cnt = int(L[lo:hi][D[lo:hi] == d].sum())
+            pools.append(uniform_values(rng, cnt, names[d], kmin, kmax).astype(UINT[names[d]])
+                         .view(np.uint8))
+        for s in range(lo, hi):
+            d = int(D[s])
+            nb = int(L[s]) * ITEMSIZE[names[d]]
             o = int(offs[s])
-            buf[o:o + v.nbytes] = v.view(np.uint8)
+            buf[o:o + nb] = pools[d][taken[d]:taken[d] + nb]
+            taken[d] += nb
 
     with ThreadPoolExecutor(_threads()) as ex:
         list(ex.map(work, range(len(children))))
