@@ -268,6 +268,57 @@ xsum_status_t xsum_segmented_capture(const xsum_plan_t *plan, const void *base,
 xsum_status_t xsum_graph_launch(void *graph_exec, void *stream);
 void xsum_graph_destroy(void *graph_exec);
 
+/* ------------------------------------------------------------------------
+ * Serving batches: one launch adds chunks of many requests into per-request
+ * device states that persist across launches (continuous batching); a second
+ * launch rounds the states of the requests that are complete.
+ * ------------------------------------------------------------------------ */
+
+/* One request's contribution to a batch (32 bytes, in device memory).
+ *   ptr         device address of the first element, element-aligned
+ *   length      elements
+ *   dtype       XSUM_F64, XSUM_F32 or XSUM_BF16
+ *   slot        index of the destination xsum_acc_t in `states`
+ *   first_task  sum of xsum_batch_item_tasks() over the preceding items
+ * Items must be ordered by first_task; they are trusted as given. */
+typedef struct xsum_batch_item {
+    uint64_t ptr;
+    uint64_t length;
+    uint32_t dtype;
+    uint32_t slot;
+    uint64_t first_task;
+} xsum_batch_item_t;
+
+/* Number of work items (chunks of chunk_vectors 16-byte vectors) that one
+ * batch item takes; at least 1.  Host function, no device access. */
+uint64_t xsum_batch_item_tasks(uint64_t ptr, uint64_t length, int dtype,
+                               uint64_t chunk_vectors);
+
+/*
+ * states[item.slot] += exact sum of the item's elements, for every item, in
+ * one persistent launch on `stream`.  Items sharing a slot are all added.
+ *   items        device array of nitems items
+ *   ntasks       total work items (sum of xsum_batch_item_tasks), < 2^32
+ *   chunk_vectors the value used for xsum_batch_item_tasks, in [64, 2^26]
+ *   states       device states; a state may take at most 2^20 batches
+ *                between two finalizations
+ *   ctl          device, 256 bytes, zeroed once before first use; every
+ *                completed launch leaves it zeroed.  Launches sharing ctl
+ *                must be ordered.
+ */
+xsum_status_t xsum_batch_add(const xsum_batch_item_t *items, uint32_t nitems,
+                             uint64_t ntasks, uint64_t chunk_vectors,
+                             xsum_acc_t *states, void *ctl, void *stream);
+
+/*
+ * For i < n: round states[slots[i]] once to fmts[i] (XSUM_F64/F32/BF16), write
+ * the bit pattern zero-extended into out[i] (8-byte slots) and the flags into
+ * flags[i] (may be NULL), then zero the state.  One launch on `stream`.
+ */
+xsum_status_t xsum_batch_finalize(const uint32_t *slots, const uint32_t *fmts,
+                                  uint32_t n, xsum_acc_t *states, void *out,
+                                  uint32_t *flags, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

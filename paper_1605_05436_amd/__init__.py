@@ -32,8 +32,15 @@ EXPORTED = [
     "xsum_segmented_plan", "xsum_plan_destroy", "xsum_plan_get_info",
     "xsum_segmented_workspace_size", "xsum_segmented_workspace_init",
     "xsum_segmented_run", "xsum_segmented_capture", "xsum_graph_launch",
-    "xsum_graph_destroy",
+    "xsum_graph_destroy", "xsum_batch_item_tasks", "xsum_batch_add",
+    "xsum_batch_finalize",
 ]
+
+# xsum_batch_item_t as a numpy record (32 bytes)
+def batch_item_dtype():
+    import numpy as np
+    return np.dtype([("ptr", "<u8"), ("length", "<u8"), ("dtype", "<u4"),
+                     ("slot", "<u4"), ("first_task", "<u8")])
 
 
 class SegTuning(ctypes.Structure):
@@ -108,6 +115,12 @@ def _load():
     lib.xsum_graph_launch.argtypes = [vp, vp]
     lib.xsum_graph_destroy.restype = None
     lib.xsum_graph_destroy.argtypes = [vp]
+    lib.xsum_batch_item_tasks.restype = u64
+    lib.xsum_batch_item_tasks.argtypes = [u64, u64, i32, u64]
+    lib.xsum_batch_add.restype = i32
+    lib.xsum_batch_add.argtypes = [vp, ctypes.c_uint32, u64, u64, vp, vp, vp]
+    lib.xsum_batch_finalize.restype = i32
+    lib.xsum_batch_finalize.argtypes = [vp, vp, ctypes.c_uint32, vp, vp, vp, vp]
     return lib
 
 
@@ -229,6 +242,20 @@ def xsum_graph_launch(graph, stream=0):
 
 def xsum_graph_destroy(graph):
     _lib.xsum_graph_destroy(_p(graph))
+
+
+def xsum_batch_item_tasks(ptr, length, dtype, chunk_vectors):
+    return int(_lib.xsum_batch_item_tasks(ptr, length, dtype, chunk_vectors))
+
+
+def xsum_batch_add(items, nitems, ntasks, chunk_vectors, states, ctl, stream=0):
+    _check(_lib.xsum_batch_add(_p(items), nitems, ntasks, chunk_vectors, _p(states),
+                               _p(ctl), _p(stream)))
+
+
+def xsum_batch_finalize(slots, fmts, n, states, out, flags, stream=0):
+    _check(_lib.xsum_batch_finalize(_p(slots), _p(fmts), n, _p(states), _p(out),
+                                    _p(flags), _p(stream)))
 
 
 # ----------------------------------------------------- torch marshalling --

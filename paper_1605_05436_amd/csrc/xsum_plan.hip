@@ -24,6 +24,13 @@ uint64_t segmented_chunk_vectors();
 xsum_status_t api_fail(xsum_status_t st, const std::string &msg);
 xsum_status_t api_hip_fail(hipError_t e, const char *what);
 xsum_status_t api_current_cus(int *dev, int *cus);
+hipError_t launch_batch_add(const BatchItem *items, uint32_t nitems,
+                            uint64_t ntasks, uint64_t chunk_vectors,
+                            xsum_acc_t *states, SegCtl *ctl, int blocks,
+                            hipStream_t stream);
+hipError_t launch_batch_finalize(const uint32_t *slots, const uint32_t *fmts,
+                                 uint32_t n, xsum_acc_t *states, uint64_t *out,
+                                 uint32_t *flags, hipStream_t stream);
 }  // namespace xsum
 
 struct xsum_plan {
@@ -378,6 +385,57 @@ void xsum_graph_destroy(void *graph_exec)
 {
     if (graph_exec)
         (void)hipGraphExecDestroy((hipGraphExec_t)graph_exec);
+}
+
+uint64_t xsum_batch_item_tasks(uint64_t ptr, uint64_t length, int dtype,
+                               uint64_t chunk_vectors)
+{
+    if (dtype < 0 || dtype > 2 || chunk_vectors == 0)
+        return 1;
+    uint64_t head = ((16 - (ptr & 15)) & 15) / (uint64_t)kBytes[dtype];
+    if (head > length)
+        head = length;
+    const uint64_t nvs = (length - head) / (uint64_t)kPerVec[dtype];
+    const uint64_t nch = (nvs + chunk_vectors - 1) / chunk_vectors;
+    return nch ? nch : 1;
+}
+
+xsum_status_t xsum_batch_add(const xsum_batch_item_t *items, uint32_t nitems,
+                             uint64_t ntasks, uint64_t chunk_vectors,
+                             xsum_acc_t *states, void *ctl, void *stream)
+{
+    if (nitems == 0 || ntasks == 0)
+        return XSUM_OK;
+    if (items == nullptr || states == nullptr || ctl == nullptr)
+        return api_fail(XSUM_EINVAL, "items, states or ctl is NULL");
+    if (ntasks >= (1ull << 32) - 65536)
+        return api_fail(XSUM_ERANGE, "too many work items in one batch");
+    if (chunk_vectors < 64 || chunk_vectors > (1ull << 26))
+        return api_fail(XSUM_ERANGE, "chunk_vectors out of range [64, 2^26]");
+    int dev, cus;
+    xsum_status_t st = xsum::api_current_cus(&dev, &cus);
+    if (st != XSUM_OK)
+        return st;
+    uint64_t blocks = 4ull * (uint64_t)cus;
+    if (blocks > ntasks)
+        blocks = ntasks;
+    hipError_t e = xsum::launch_batch_add((const xsum::BatchItem *)items, nitems, ntasks,
+                                          chunk_vectors, states, (xsum::SegCtl *)ctl,
+                                          (int)blocks, (hipStream_t)stream);
+    return e == hipSuccess ? XSUM_OK : api_hip_fail(e, "kernel launch");
+}
+
+xsum_status_t xsum_batch_finalize(const uint32_t *slots, const uint32_t *fmts,
+                                  uint32_t n, xsum_acc_t *states, void *out,
+                                  uint32_t *flags, void *stream)
+{
+    if (n == 0)
+        return XSUM_OK;
+    if (slots == nullptr || fmts == nullptr || states == nullptr || out == nullptr)
+        return api_fail(XSUM_EINVAL, "slots, fmts, states or out is NULL");
+    hipError_t e = xsum::launch_batch_finalize(slots, fmts, n, states, (uint64_t *)out,
+                                               flags, (hipStream_t)stream);
+    return e == hipSuccess ? XSUM_OK : api_hip_fail(e, "kernel launch");
 }
 
 }  // extern "C"

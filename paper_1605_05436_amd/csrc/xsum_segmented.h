@@ -45,4 +45,13 @@ struct SegCtl {
 
 static constexpr uint64_t kSegCtlBytes = sizeof(SegCtl);
 
+// One request chunk list of a serving batch (same layout as xsum_batch_item_t).
+struct BatchItem {
+    uint64_t ptr;         // device address of the first element
+    uint64_t length;      // elements
+    uint32_t dtype;
+    uint32_t slot;        // destination state
+    uint64_t first_task;  // index of the item's first chunk among all tasks
+};
+
 }  // namespace xsum

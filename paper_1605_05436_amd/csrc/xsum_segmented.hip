@@ -447,6 +447,120 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
     }
 }
 
+// ------------------------------------------------------ serving batches --
+//
+// One launch adds every chunk of every item of a batch into the item's
+// destination state (Section 6: reducers accumulate into superaccumulators
+// that are merged later; here the state persists across launches and is
+// rounded by batch_finalize_kernel once the request is complete).  Task t is
+// chunk t - first_task of the item found by binary search over first_task.
+
+template <int FMT, int UC>
+__device__ __forceinline__ void run_batch_chunk(const BatchItem &it, uint64_t c,
+                                                uint64_t chunk_vectors,
+                                                xsum_acc_t *states, WaveLds &w,
+                                                uint64_t *col, int lane)
+{
+    using G = Geo<FMT>;
+    const SegDesc d{0, it.length, it.dtype, 0};
+    const SpanGeom g = span_geom<FMT>((const uint8_t *)it.ptr, d);
+    const uint64_t v0 = c * chunk_vectors;
+    const uint64_t nv = v0 < g.nvs ? min(chunk_vectors, g.nvs - v0) : 0;
+    const uint64_t nch = g.nvs == 0 ? 1 : (g.nvs + chunk_vectors - 1) / chunk_vectors;
+    const vec4u *vp = (const vec4u *)(g.p + g.head * G::kBytes) + v0;
+    uint32_t spec = 0;
+    accumulate_span<FMT, UC>(vp, nv, g.p, c == 0 ? g.head : 0,
+                             g.p + g.head * G::kBytes + g.nvs * 16,
+                             c + 1 == nch ? g.tail : 0, col, spec, lane);
+    merge_and_clear<FMT>(w, col, lane);
+    spec = wave_or_u32(spec);
+    xsum_acc_t *st = &states[it.slot];
+    for (int k = lane; k < kDigits; k += 64) {
+        const int64_t dv = w.merged[k];
+        if (dv)
+            atomicAdd((unsigned long long *)&st->digit[k], (unsigned long long)dv);
+    }
+    if (lane == 0 && spec)
+        atomicOr(&st->special, spec);
+}
+
+template <int UC>
+__global__ __launch_bounds__(64) void batch_add_kernel(
+    const BatchItem *__restrict__ items, uint32_t nitems, uint64_t ntasks,
+    uint64_t chunk_vectors, xsum_acc_t *states, SegCtl *ctl)
+{
+    __shared__ WaveLds w;
+    const int lane = threadIdx.x;
+    uint64_t *col = &w.cols[0][lane];
+    zero_column<XSUM_F64>(col);
+    for (;;) {
+        uint32_t t32 = 0;
+        if (lane == 0)
+            t32 = atomicAdd(&ctl->head, 1u);
+        const uint64_t t = __shfl(t32, 0, 64);
+        if (t >= ntasks)
+            break;
+        // last item whose first_task <= t
+        uint32_t lo = 0, hi = nitems;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (items[mid].first_task <= t)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const BatchItem it = items[lo];
+        const uint64_t c = t - it.first_task;
+        if (it.dtype == XSUM_F64)
+            run_batch_chunk<XSUM_F64, UC>(it, c, chunk_vectors, states, w, col, lane);
+        else if (it.dtype == XSUM_F32)
+            run_batch_chunk<XSUM_F32, UC>(it, c, chunk_vectors, states, w, col, lane);
+        else
+            run_batch_chunk<XSUM_BF16, UC>(it, c, chunk_vectors, states, w, col, lane);
+    }
+    if (lane == 0) {
+        const uint32_t total = gridDim.x;
+        if (atomicAdd(&ctl->done, 1u) == total - 1) {
+            __hip_atomic_store(&ctl->head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// One wave per entry: round states[slots[i]] to its format, write out[i] /
+// flags[i] (8-byte slots), then zero the state for the next request.
+__global__ __launch_bounds__(64) void batch_finalize_kernel(
+    const uint32_t *__restrict__ slots, const uint32_t *__restrict__ fmts,
+    uint32_t n, xsum_acc_t *states, uint64_t *out, uint32_t *flags)
+{
+    const uint32_t i = blockIdx.x;
+    if (i >= n)
+        return;
+    const int lane = threadIdx.x;
+    xsum_acc_t *st = &states[slots[i]];
+    Finish fin{kRound, (int)fmts[i], out + i, flags ? flags + i : nullptr, 1};
+    finish_state(st, fin, lane);
+}
+
+hipError_t launch_batch_add(const BatchItem *items, uint32_t nitems,
+                            uint64_t ntasks, uint64_t chunk_vectors,
+                            xsum_acc_t *states, SegCtl *ctl, int blocks,
+                            hipStream_t stream)
+{
+    hipLaunchKernelGGL((batch_add_kernel<16>), dim3((unsigned)blocks), dim3(64), 0,
+                       stream, items, nitems, ntasks, chunk_vectors, states, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const uint32_t *slots, const uint32_t *fmts,
+                                 uint32_t n, xsum_acc_t *states, uint64_t *out,
+                                 uint32_t *flags, hipStream_t stream)
+{
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(n), dim3(64), 0, stream, slots,
+                       fmts, n, states, out, flags);
+    return hipGetLastError();
+}
+
 static constexpr int kSegWaves = 1;
 static constexpr int kSegLaneUnroll = 16;
 static constexpr int kSegChunkUnroll = 16;
