@@ -155,3 +155,21 @@ def test_graph_replay_matches_eager():
     finally:
         xs.xsum_graph_destroy(graph)
         ss.close()
+
+
+def test_autotuner_picks_a_candidate_with_identical_results(tmp_path, monkeypatch):
+    import torch
+    import paper_1605_05436_amd as xs
+    from paper_1605_05436_amd import autotune
+    monkeypatch.setenv("XSUM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    buf, desc = workloads.config4(nseg=4000, seed=11)
+    dbuf = torch.from_numpy(buf).to("cuda")
+    cands = autotune.DEFAULT_CANDIDATES[:4]
+    best, table = autotune.tune_segmented(desc, dbuf, candidates=cands, reps=2)
+    assert best in cands and len(table) == len(cands)
+    # cached: the second call returns the same choice without timing
+    best2, _ = autotune.tune_segmented(desc, dbuf, candidates=cands, reps=2)
+    assert best2 == best
+    want = expected(buf, desc)
+    results, _ = run_gpu(buf, desc, tuning=autotune.tuning_struct(best))
+    assert np.array_equal(results[0][0], want[0]) and np.array_equal(results[0][1], want[1])
