@@ -67,12 +67,40 @@ class XsumError(RuntimeError):
         self.status = status
 
 
+def _hip_runtimes_loaded():
+    """Distinct libamdhip64 files mapped into this process (Linux)."""
+    try:
+        with open("/proc/self/maps") as f:
+            maps = f.read()
+    except OSError:
+        return []
+    found = set()
+    for line in maps.splitlines():
+        path = line.split()[-1] if line.split() else ""
+        if os.path.basename(path).startswith("libamdhip64.so"):
+            found.add(os.path.realpath(path))
+    return sorted(found)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             "libxsum.so is not built (expected at %s); run "
             "`python paper_1605_05436_amd/build.py`" % LIB_PATH)
+    # The library must run on the same HIP runtime as the PyTorch tensors it
+    # is handed.  PyTorch ships its own libamdhip64.so.7; loading torch first
+    # lets the dynamic loader bind libxsum's dependency of that soname to the
+    # copy already in the process instead of loading a second runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes_loaded()
+    if len(runtimes) > 1:
+        raise ImportError("two HIP runtimes are loaded in this process (%s); "
+                          "libxsum would not see the same devices and memory "
+                          "as PyTorch" % ", ".join(runtimes))
     vp, u64, i32, u32p = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, \
         ctypes.POINTER(ctypes.c_uint32)
     lib.xsum_version.restype = ctypes.c_char_p

@@ -21,6 +21,10 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-function",
     # no packed-FP32 instructions are to be generated in any HIP code here
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep single-lane queue atomics as written: the optimiser's rewrite reads
+    # the result back at once, which would serialise the pop of the next work
+    # item with the current one instead of overlapping them
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

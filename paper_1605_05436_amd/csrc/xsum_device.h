@@ -252,18 +252,23 @@ __device__ __forceinline__ void normalise_column(uint64_t *col)
         lds_store(col + d * 64, (uint64_t)v[d]);
 }
 
-// Block merge of one wave's columns.  Lane l takes column entry l (and
-// l+64): it sums that entry over the wave's 64 lanes, reading lane
-// (c + l) mod 64 so the 64 lanes hit distinct banks.  Each entry splits as
-// lo + hi 2^32 (lo in [0, 2^32)) before summing so nothing can overflow; the
-// sums go to the block's digit vector blk with LDS atomics.  Binary32 bins
-// (weight 2^(8b)) are first moved to their radix-2^32 digit.
+// Block merge of one wave's columns.  Lane l takes column entry l: it sums
+// that entry over the wave's 64 lanes, reading lane (c + l) mod 64 so the 64
+// lanes hit distinct banks.  Each entry splits as lo + hi 2^32 (lo in
+// [0, 2^32)) before summing so nothing can overflow; the sums go to the
+// block's digit vector blk with LDS atomics.  Binary32 bins (weight 2^(8b))
+// are first moved to their radix-2^32 digit.  Binary64 entries 64 and 65 only
+// receive chunks of inputs of magnitude 2^994 and above (and their carries),
+// so instead of a second pass each lane adds its own two top entries, and only
+// when one of them is non-zero anywhere in the wave.
 template <int FMT>
 __device__ __forceinline__ void merge_wave_columns(uint64_t (*cols)[64],
                                                    int64_t *blk, int lane)
 {
     using G = Geo<FMT>;
-    for (int d = lane; d < G::kN; d += 64) {
+    static_assert(G::kN <= 66, "at most two entries above the lanes");
+    if (lane < G::kN) {
+        const int d = lane;
         const uint64_t *row = cols[d];
         uint64_t lo = 0;
         int64_t hi = 0;
@@ -293,6 +298,28 @@ __device__ __forceinline__ void merge_wave_columns(uint64_t (*cols)[64],
             if (parts[i])
                 __hip_atomic_fetch_add(&blk[digit + i], parts[i],
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    if constexpr (G::kN > 64) {
+        uint64_t top[G::kN - 64];
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < G::kN - 64; ++r) {
+            top[r] = cols[64 + r][lane];
+            any |= top[r] != 0;
+        }
+        if (__ballot(any)) {
+#pragma unroll
+            for (int r = 0; r < G::kN - 64; ++r) {
+                const int64_t lo = (int64_t)(top[r] & kLow32);
+                const int64_t hi = (int64_t)top[r] >> 32;
+                if (lo)
+                    __hip_atomic_fetch_add(&blk[64 + r], lo, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (hi)
+                    __hip_atomic_fetch_add(&blk[65 + r], hi, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
     }
 }
 

@@ -15,8 +15,8 @@
 
 namespace xsum {
 hipError_t launch_segmented(const void *base, const SegDesc *segs,
-                            const SegTask *tasks, uint32_t ntasks,
-                            const uint32_t *perm, xsum_acc_t *states,
+                            const SegTask *tasks, uint32_t ntasks, uint32_t small_from,
+                            const SegLane *lanes, xsum_acc_t *states,
                             SegCtl *ctl, int out_mode, uint64_t *out,
                             uint32_t *flags, int blocks, hipStream_t stream);
 int segmented_blocks(int cu_count, int blocks_per_cu);
@@ -39,8 +39,9 @@ struct xsum_plan {
     int out_mode = XSUM_SAME;
     xsum::SegDesc *d_segs = nullptr;
     xsum::SegTask *d_tasks = nullptr;
-    uint32_t *d_perm = nullptr;
+    xsum::SegLane *d_lanes = nullptr;
     uint32_t ntasks = 0, nslots = 0;
+    uint32_t small_from = 0;  // first item that may be claimed with its neighbours
     int blocks = 0;
     xsum_plan_info_t info{};
 };
@@ -54,7 +55,7 @@ constexpr int kPerVec[3] = {2, 4, 8};
 constexpr int kBytes[3] = {8, 4, 2};
 // Default per-lane limits: segments up to this many elements are summed one
 // per lane (64 KiB of input per lane).
-constexpr uint64_t kLaneMaxDefault[3] = {8192, 16384, 32768};
+constexpr uint64_t kLaneMaxDefault[3] = {4096, 8192, 16384};
 // Segments up to 4 MiB are summed whole by one wave.
 constexpr uint64_t kWaveMaxDefault[3] = {1ull << 19, 1ull << 20, 1ull << 21};
 
@@ -66,8 +67,8 @@ void free_plan(xsum_plan *p)
         (void)hipFree(p->d_segs);
     if (p->d_tasks)
         (void)hipFree(p->d_tasks);
-    if (p->d_perm)
-        (void)hipFree(p->d_perm);
+    if (p->d_lanes)
+        (void)hipFree(p->d_lanes);
     delete p;
 }
 
@@ -143,7 +144,7 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
         uint64_t cost;  // estimated time: vectors one lane walks through
     };
     std::vector<HostTask> tasks;
-    std::vector<uint32_t> perm;
+    std::vector<xsum::SegLane> lanes;
     // long segments: chunks of chunk_vectors 16-byte vectors, one state each
     uint32_t slots = 0;
     uint64_t nchunks_total = 0;
@@ -180,6 +181,8 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
         HostTask h{};
         h.t.kind_dtype_flags = xsum::kWhole | (dt << 8);
         h.t.a = id;
+        h.t.v0 = segs[id].byte_offset;
+        h.t.nv = segs[id].length;
         h.cost = segs[id].length / kPerVec[dt] / 64 + 1;
         tasks.push_back(h);
     }
@@ -210,20 +213,22 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
             const size_t cnt = std::min<size_t>(64, ids.size() - g);
             HostTask h{};
             h.t.kind_dtype_flags = xsum::kLaneGroup | ((uint32_t)dt << 8);
-            h.t.a = (uint32_t)perm.size();
+            h.t.a = (uint32_t)lanes.size();
             h.t.b = (uint32_t)cnt;
             uint64_t maxlen = 0;
             for (size_t k = g; k < g + cnt; ++k)
                 maxlen = std::max<uint64_t>(maxlen, segs[ids[k]].length);
             h.cost = maxlen / kPerVec[dt] + 1;
             tasks.push_back(h);
-            perm.insert(perm.end(), ids.begin() + g, ids.begin() + g + cnt);
+            for (size_t k = g; k < g + cnt; ++k)
+                lanes.push_back({segs[ids[k]].byte_offset, (uint32_t)segs[ids[k]].length, ids[k]});
         }
     }
     // longest work first, so the queue drains evenly
     std::stable_sort(tasks.begin(), tasks.end(),
                      [](const HostTask &x, const HostTask &y) { return x.cost > y.cost; });
-    if (tasks.size() >= (1ull << 32) - 4096)
+    // the queue counter runs past the last item by a few claims per wave
+    if (tasks.size() >= (1ull << 31))
         return api_fail(XSUM_ERANGE, "too many work items");
 
     int dev, cus;
@@ -237,6 +242,19 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
     p->ntasks = (uint32_t)tasks.size();
     p->nslots = slots;
     p->blocks = xsum::segmented_blocks(cus, blocks_per_cu);
+    // Items are claimed one at a time while they are large (longest first is
+    // what balances the waves) and several at a time once an item is below
+    // 1/16 of a wave's share of the estimated work.
+    {
+        long double total = 0;
+        for (const HostTask &h : tasks)
+            total += (long double)h.cost;
+        const long double share = total / (long double)std::max(1, p->blocks);
+        uint32_t i = 0;
+        while (i < p->ntasks && (long double)tasks[i].cost * 16 >= share)
+            ++i;
+        p->small_from = i;
+    }
     p->info.nseg = nseg;
     p->info.lane_segments = lane_ids[0].size() + lane_ids[1].size() + lane_ids[2].size();
     p->info.wave_segments = wave_ids.size();
@@ -259,15 +277,15 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
         e = hipMalloc((void **)&p->d_segs, nseg * sizeof(xsum::SegDesc));
     if (e == hipSuccess && !flat.empty())
         e = hipMalloc((void **)&p->d_tasks, flat.size() * sizeof(xsum::SegTask));
-    if (e == hipSuccess && !perm.empty())
-        e = hipMalloc((void **)&p->d_perm, perm.size() * sizeof(uint32_t));
+    if (e == hipSuccess && !lanes.empty())
+        e = hipMalloc((void **)&p->d_lanes, lanes.size() * sizeof(xsum::SegLane));
     if (e == hipSuccess && nseg)
         e = hipMemcpy(p->d_segs, segs, nseg * sizeof(xsum::SegDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess && !flat.empty())
         e = hipMemcpy(p->d_tasks, flat.data(), flat.size() * sizeof(xsum::SegTask),
                       hipMemcpyHostToDevice);
-    if (e == hipSuccess && !perm.empty())
-        e = hipMemcpy(p->d_perm, perm.data(), perm.size() * sizeof(uint32_t),
+    if (e == hipSuccess && !lanes.empty())
+        e = hipMemcpy(p->d_lanes, lanes.data(), lanes.size() * sizeof(xsum::SegLane),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         free_plan(p);
@@ -317,8 +335,8 @@ xsum_status_t xsum_segmented_run(const xsum_plan_t *plan, const void *base,
     if (dev != plan->device)
         return api_fail(XSUM_EINVAL, "plan was built for another device");
     uint8_t *ws = (uint8_t *)workspace;
-    e = xsum::launch_segmented(base, plan->d_segs, plan->d_tasks, plan->ntasks,
-                               plan->d_perm, (xsum_acc_t *)(ws + xsum::kSegCtlBytes),
+    e = xsum::launch_segmented(base, plan->d_segs, plan->d_tasks, plan->ntasks, plan->small_from,
+                               plan->d_lanes, (xsum_acc_t *)(ws + xsum::kSegCtlBytes),
                                (xsum::SegCtl *)ws, plan->out_mode, (uint64_t *)out,
                                flags, plan->blocks, (hipStream_t)stream);
     return e == hipSuccess ? XSUM_OK : api_hip_fail(e, "kernel launch");

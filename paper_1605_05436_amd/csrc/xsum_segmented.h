@@ -28,11 +28,18 @@ enum SegChunkFlags : uint32_t {
 // 32-byte work item.
 struct SegTask {
     uint32_t kind_dtype_flags;  // kind | dtype << 8 | chunk flags << 16
-    uint32_t a;                 // lane group: first perm index; else: segment
+    uint32_t a;                 // lane group: first lane entry; else: segment
     uint32_t b;                 // lane group: lane count;  chunk: state slot
     uint32_t nchunks;           // chunk: chunks of its segment
-    uint64_t v0;                // chunk: first 16-byte vector of the chunk
-    uint64_t nv;                // chunk: vectors in the chunk
+    uint64_t v0;                // whole: byte offset;  chunk: first 16-byte vector
+    uint64_t nv;                // whole: elements;     chunk: vectors in the chunk
+};
+
+// 16-byte lane entry: the segment one lane of a lane group sums.
+struct SegLane {
+    uint64_t byte_offset;
+    uint32_t length;            // at most the largest lane_max (2^23)
+    uint32_t seg;               // output index
 };
 
 // Control words at the start of the workspace.  Both return to zero at the

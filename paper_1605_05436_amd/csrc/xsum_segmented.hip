@@ -8,7 +8,7 @@
 //   * lane group: up to 64 whole segments of one format and similar length
 //     (the plan sorts segments by length).  Each lane streams its own segment
 //     into its private LDS column exactly as the single-sum kernel does, then
-//     carry-normalises and rounds it alone (LaneFinisher), so a segment costs
+//     carry-normalises and rounds it alone (finish_lane), so a segment costs
 //     about 1/64 of a wave's fixed work.
 //   * whole segment: a longer segment loaded coalesced by one wave, which
 //     merges its 64 columns, carry-normalises and rounds with no state in
@@ -31,6 +31,9 @@
 
 namespace xsum {
 
+// Work items claimed per queue atomic by the segmented kernel.
+static constexpr int kSegPopBatch = 4;
+
 template <int FMT> struct LaneOut;
 template <> struct LaneOut<XSUM_F64> { static constexpr int kNatural = XSUM_F64; };
 template <> struct LaneOut<XSUM_F32> { static constexpr int kNatural = XSUM_F32; };
@@ -46,8 +49,10 @@ struct WaveLds {
 __device__ __forceinline__ void wave_lds_fence()
 {
     // every LDS operation of this wave issued so far has completed and is
-    // ordered before what follows (other lanes' column entries are read next)
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    // ordered before what follows (other lanes' column entries are read
+    // next).  The fence names LDS only, so loads and atomics in flight to
+    // global memory (the next work item's records) are not waited for.
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup", "local");
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -123,22 +128,17 @@ __device__ __forceinline__ uint64_t finish_lane(uint64_t *col, uint32_t spec,
     }
 }
 
-// One lane group: lane l < count sums segment perm[first + l].
+// One lane group: lane l < count sums the segment of its lane entry e.
 template <int FMT, int UL>
-__device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegDesc *segs,
-                               const uint32_t *perm, uint32_t first,
-                               uint32_t count, uint64_t *col, int out_mode,
-                               uint64_t *out, uint32_t *flags, int lane)
+__device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLane &e,
+                                               uint32_t count, uint64_t *col, int out_mode,
+                                               uint64_t *out, uint32_t *flags, int lane)
 {
     using G = Geo<FMT>;
     const bool live = (uint32_t)lane < count;
-    uint32_t s = 0;
-    uint64_t L = 0, off = 0;
-    if (live) {
-        s = perm[first + lane];
-        off = segs[s].byte_offset;
-        L = segs[s].length;
-    }
+    const uint32_t s = e.seg;
+    const uint64_t off = live ? e.byte_offset : 0;
+    const uint64_t L = live ? e.length : 0;
     const uint8_t *p = base + off;
     uint64_t head = ((16 - ((uintptr_t)p & 15)) & 15) / G::kBytes;
     if (head > L)
@@ -302,14 +302,17 @@ __device__ __forceinline__ SpanGeom span_geom(const uint8_t *base,
     return g;
 }
 
-// One whole segment, summed, normalised and rounded by one wave.
+// One whole segment, summed, normalised and rounded by one wave.  Its offset
+// and length travel in the work item itself.
 template <int FMT, int UC>
-__device__ __forceinline__ void run_whole(const uint8_t *base, const SegDesc *segs, uint32_t s,
-                          WaveLds &w, uint64_t *col, int out_mode,
-                          uint64_t *out, uint32_t *flags, int lane)
+__device__ __forceinline__ void run_whole(const uint8_t *base, const SegTask &t,
+                                          WaveLds &w, uint64_t *col, int out_mode,
+                                          uint64_t *out, uint32_t *flags, int lane)
 {
     using G = Geo<FMT>;
-    const SpanGeom g = span_geom<FMT>(base, segs[s]);
+    const uint32_t s = t.a;
+    const SegDesc d{t.v0, t.nv, 0, 0};
+    const SpanGeom g = span_geom<FMT>(base, d);
     const vec4u *vp = (const vec4u *)(g.p + g.head * G::kBytes);
     uint32_t spec = 0;
     accumulate_span<FMT, UC>(vp, g.nvs, g.p, g.head,
@@ -373,11 +376,23 @@ __device__ __forceinline__ void run_chunk(const uint8_t *base, const SegDesc *se
     }
 }
 
+// The lane entry of work item t for this lane (zero when t is not a lane
+// group or the lane is past its count).
+__device__ __forceinline__ SegLane lane_entry(const SegLane *__restrict__ lanes,
+                                              const SegTask &t, uint32_t ntasks_left,
+                                              int lane)
+{
+    SegLane e{0, 0, 0};
+    if (ntasks_left && (t.kind_dtype_flags & 0xffu) == kLaneGroup && (uint32_t)lane < t.b)
+        e = lanes[t.a + lane];
+    return e;
+}
+
 template <int WAVES, int UL, int UC>
 __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
     const uint8_t *__restrict__ base, const SegDesc *__restrict__ segs,
-    const SegTask *__restrict__ tasks, uint32_t ntasks,
-    const uint32_t *__restrict__ perm, xsum_acc_t *states, SegCtl *ctl,
+    const SegTask *__restrict__ tasks, uint32_t ntasks, uint32_t small_from,
+    const SegLane *__restrict__ lanes, xsum_acc_t *states, SegCtl *ctl,
     int out_mode, uint64_t *out, uint32_t *flags)
 {
     __shared__ WaveLds lds[WAVES];
@@ -386,43 +401,71 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
     uint64_t *col = &w.cols[0][lane];
     zero_column<XSUM_F64>(col);
 
-    // the next item is popped as soon as the current one is known, so the
-    // atomic's round trip overlaps with the current item's work
-    uint32_t cur = 0, next = 0;
+    // Items are claimed from the queue one at a time while they are large
+    // (longest first is what balances the waves), and kSegPopBatch at a time
+    // from item small_from on, where items are short.  The next claim is made
+    // while the current one is handed out: a device-scope atomic's round trip
+    // is long and its result is waited for where it is taken, so one wait
+    // then serves several short items.
+    uint32_t b0 = 0, n0 = 1, b1 = 0, n1 = 1, bi = 0;
     if (lane == 0) {
-        cur = atomicAdd(&ctl->head, 1u);
-        next = atomicAdd(&ctl->head, 1u);
+        b0 = atomicAdd(&ctl->head, 1u);
+        b1 = atomicAdd(&ctl->head, 1u);
     }
-    cur = __shfl(cur, 0, 64);
-    SegTask t{};
+    b0 = __shfl(b0, 0, 64);
+    b1 = __shfl(b1, 0, 64);
+    // next item index; each wave's indices only grow, so the first one past
+    // the end ends the wave's work
+    auto draw = [&]() -> uint32_t {
+        if (bi == n0) {
+            b0 = b1;
+            n0 = n1;
+            bi = 0;
+            n1 = b0 >= small_from ? (uint32_t)kSegPopBatch : 1u;
+            uint32_t claimed = 0;
+            if (lane == 0)
+                claimed = atomicAdd(&ctl->head, n1);
+            b1 = __shfl(claimed, 0, 64);
+        }
+        return b0 + bi++;
+    };
+
+    // Work items flow through a three-stage pipeline so that no dependent
+    // global access stands between two items: while item i runs, the record
+    // and lane entry of item i + 1 and the record of item i + 2 are already
+    // in registers or in flight.
+    uint32_t cur = draw();
+    uint32_t next = draw();
+    uint32_t after = draw();
+    SegTask t{}, nt{};
     if (cur < ntasks)
         t = tasks[cur];
-    next = __shfl(next, 0, 64);
+    if (next < ntasks)
+        nt = tasks[next];
+    SegLane e = lane_entry(lanes, t, cur < ntasks, lane);
     while (cur < ntasks) {
-        // the record of the following item is fetched and the item after it
-        // popped while this one runs
-        SegTask nt{};
-        if (next < ntasks)
-            nt = tasks[next];
-        uint32_t nn = 0;
-        if (lane == 0)
-            nn = atomicAdd(&ctl->head, 1u);
+        // issued before the item's own loads, consumed at the next item
+        const SegLane ne = lane_entry(lanes, nt, next < ntasks, lane);
+        SegTask nnt{};
+        if (after < ntasks)
+            nnt = tasks[after];
+        const uint32_t following = draw();
         const uint32_t kind = t.kind_dtype_flags & 0xffu;
         const uint32_t dtype = (t.kind_dtype_flags >> 8) & 0xffu;
         if (kind == kLaneGroup) {
             if (dtype == XSUM_F64)
-                run_lane_group<XSUM_F64, UL>(base, segs, perm, t.a, t.b, col, out_mode, out, flags, lane);
+                run_lane_group<XSUM_F64, UL>(base, e, t.b, col, out_mode, out, flags, lane);
             else if (dtype == XSUM_F32)
-                run_lane_group<XSUM_F32, UL>(base, segs, perm, t.a, t.b, col, out_mode, out, flags, lane);
+                run_lane_group<XSUM_F32, UL>(base, e, t.b, col, out_mode, out, flags, lane);
             else
-                run_lane_group<XSUM_BF16, UL>(base, segs, perm, t.a, t.b, col, out_mode, out, flags, lane);
+                run_lane_group<XSUM_BF16, UL>(base, e, t.b, col, out_mode, out, flags, lane);
         } else if (kind == kWhole) {
             if (dtype == XSUM_F64)
-                run_whole<XSUM_F64, UC>(base, segs, t.a, w, col, out_mode, out, flags, lane);
+                run_whole<XSUM_F64, UC>(base, t, w, col, out_mode, out, flags, lane);
             else if (dtype == XSUM_F32)
-                run_whole<XSUM_F32, UC>(base, segs, t.a, w, col, out_mode, out, flags, lane);
+                run_whole<XSUM_F32, UC>(base, t, w, col, out_mode, out, flags, lane);
             else
-                run_whole<XSUM_BF16, UC>(base, segs, t.a, w, col, out_mode, out, flags, lane);
+                run_whole<XSUM_BF16, UC>(base, t, w, col, out_mode, out, flags, lane);
         } else {
             if (dtype == XSUM_F64)
                 run_chunk<XSUM_F64, UC>(base, segs, t, states, w, col, out_mode, out, flags, lane);
@@ -432,12 +475,15 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
                 run_chunk<XSUM_BF16, UC>(base, segs, t, states, w, col, out_mode, out, flags, lane);
         }
         cur = next;
+        next = after;
+        after = following;
         t = nt;
-        next = __shfl(nn, 0, 64);
+        nt = nnt;
+        e = ne;
     }
     // The last wave out resets the queue for the next launch.  Every wave's
-    // final pop returned before its exit increment was issued, so no fence
-    // is needed here.
+    // claims have returned before its exit increment is issued (each result
+    // was read above), so no fence is needed here.
     if (lane == 0) {
         const uint32_t total = gridDim.x * WAVES;
         if (atomicAdd(&ctl->done, 1u) == total - 1) {
@@ -572,14 +618,14 @@ int segmented_blocks(int cu_count, int blocks_per_cu)
 }
 
 hipError_t launch_segmented(const void *base, const SegDesc *segs,
-                            const SegTask *tasks, uint32_t ntasks,
-                            const uint32_t *perm, xsum_acc_t *states,
+                            const SegTask *tasks, uint32_t ntasks, uint32_t small_from,
+                            const SegLane *lanes, xsum_acc_t *states,
                             SegCtl *ctl, int out_mode, uint64_t *out,
                             uint32_t *flags, int blocks, hipStream_t stream)
 {
     hipLaunchKernelGGL((segmented_kernel<kSegWaves, kSegLaneUnroll, kSegChunkUnroll>),
                        dim3((unsigned)blocks), dim3(kSegWaves * 64), 0, stream,
-                       (const uint8_t *)base, segs, tasks, ntasks, perm, states,
+                       (const uint8_t *)base, segs, tasks, ntasks, small_from, lanes, states,
                        ctl, out_mode, out, flags);
     return hipGetLastError();
 }

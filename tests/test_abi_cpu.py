@@ -24,6 +24,11 @@ def declared_functions():
 def lib():
     if not os.path.exists(LIB):
         pytest.fail("libxsum.so is not built; run __graft_entry__.build()")
+    # as in the binding: torch's HIP runtime first, so the library binds to it
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     return ctypes.CDLL(LIB)
 
 
@@ -100,3 +105,17 @@ def test_bad_output_dtype_and_null_state(lib):
                                          ctypes.c_void_p(8192), None,
                                          ctypes.c_void_p(16384), -1, None)
     assert st == 1
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the binding before torch must not load a second HIP
+    runtime (torch bundles its own libamdhip64)."""
+    import subprocess
+    import sys
+    code = ("import paper_1605_05436_amd as xs, torch, ctypes; "
+            "print(len(xs._hip_runtimes_loaded()))")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1"
