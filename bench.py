@@ -45,24 +45,30 @@ KERNEL_SOURCES = ["paper_1605_05436_amd/csrc/xsum_kernels.hip",
                   "paper_1605_05436_amd/csrc/xsum_device.h",
                   "paper_1605_05436_amd/csrc/xsum_internal.h"]
 TRAFFIC_PROFILE = "profiles/accumulate_f64_n2e28_hbm_counters.md"
+SEG_KERNEL_SOURCES = ["paper_1605_05436_amd/csrc/xsum_segmented.hip",
+                      "paper_1605_05436_amd/csrc/xsum_segmented.h",
+                      "paper_1605_05436_amd/csrc/xsum_plan.hip",
+                      "paper_1605_05436_amd/csrc/xsum_device.h"]
+SEG_TRAFFIC_PROFILE = "profiles/segmented_c4_1e6seg_hbm_counters.md"
 
 
-def measured_traffic(n):
-    """HBM bytes per launch of the binary64 kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source
-    and this n; otherwise None."""
+def measured_traffic(n, sources=KERNEL_SOURCES, profile=TRAFFIC_PROFILE, match=None):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source, this workload size n and (when
+    given) the same plan settings; otherwise None."""
     import hashlib
     h = hashlib.sha256()
     try:
-        for f in KERNEL_SOURCES:
+        for f in sources:
             h.update(open(os.path.join(ROOT, f), "rb").read())
-        text = open(os.path.join(ROOT, TRAFFIC_PROFILE)).read()
+        text = open(os.path.join(ROOT, profile)).read()
     except OSError:
         return None
     for line in text.splitlines():
         if line.startswith("traffic-record:"):
             rec = json.loads(line.split(":", 1)[1])
-            if rec.get("kernel_source_sha256") == h.hexdigest()[:16] and rec.get("n") == n:
+            if rec.get("kernel_source_sha256") == h.hexdigest()[:16] and rec.get("n") == n \
+                    and all(rec.get(k) == v for k, v in (match or {}).items()):
                 return int(rec["traffic_bytes"])
     return None
 
@@ -302,7 +308,10 @@ def bench_segmented(args):
                                                         "chunked_segments", "work_items")},
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": None}}
+                        "traffic": measured_traffic(
+                            nel, SEG_KERNEL_SOURCES, SEG_TRAFFIC_PROFILE,
+                            {"tuning": [list(best[0]), list(best[1]), best[2], best[3],
+                                        best[4]]})}}
     print(json.dumps(rec), flush=True)
 
 

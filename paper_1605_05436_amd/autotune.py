@@ -103,9 +103,12 @@ def _time_candidate(desc, dbuf, cand, reps, out, flags):
 
 
 def tune_segmented(desc, dbuf, candidates=None, reps=5, use_cache=True,
-                   verbose=False):
+                   verbose=False, margin=0.03):
     """Pick the fastest tuning for this batch.  Returns (tuning tuple, table)
-    where table lists (candidate, ms).  Raises if candidates disagree."""
+    where table lists (candidate, ms).  Raises if candidates disagree.  The
+    first candidate (the library defaults) is kept unless another is faster
+    by more than `margin` (relative), so near-ties between timings resolve
+    the same way from run to run."""
     import torch
     sig = batch_signature(desc)
     path = cache_path()
@@ -131,7 +134,7 @@ def tune_segmented(desc, dbuf, candidates=None, reps=5, use_cache=True,
         table.append((cand, ms))
         if verbose:
             print("[autotune] %r: %.3f ms" % (cand, ms), flush=True)
-        if best is None or ms < best[1]:
+        if best is None or ms < best[1] * (1.0 - margin):
             best = (cand, ms)
     if use_cache:
         cache[sig] = {"tuning": [list(best[0][0]), list(best[0][1]), best[0][2],
