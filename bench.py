@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-torch-sum", action="store_true")
     ap.add_argument("--workload", default="single",
-                    choices=["single", "segmented", "serving"])
+                    choices=["single", "config3", "segmented", "serving"])
     ap.add_argument("--nseg", type=int, default=1_000_000)
     ap.add_argument("--duration", type=float, default=60.0)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -110,6 +110,8 @@ def main():
 
     if args.workload == "segmented":
         return bench_segmented(args)
+    if args.workload == "config3":
+        return bench_config3(args)
     if args.workload == "serving":
         return bench_serving(args)
 
@@ -229,6 +231,86 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
+def bench_config3(args):
+    """2^31 binary64 z * 2^k (z normal, k uniform in [-500, 500]) with one
+    subnormal or +-DBL_MAX per 1000 elements, signs of the DBL_MAX entries
+    balanced so the sum is finite: 17.2 GB read per step."""
+    import torch
+    import paper_1605_05436_amd as xs
+    import workloads
+    import oracle
+
+    n = 1 << 31
+    t0 = time.time()
+    bits = workloads.config3(n=n, seed=args.seed)
+    log("generated config 3 (n=2^31) in %.1f s" % (time.time() - t0))
+    x = torch.from_numpy(bits.view(np.int64)).to("cuda")
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    scratch = xs.new_states(1)
+    stream = torch.cuda.current_stream()
+    sh = xs.stream_handle(stream)
+
+    def step():
+        xs.xsum_exact_sum_async(x.data_ptr(), n, xs.F64, xs.F64, out.data_ptr(),
+                                flags.data_ptr(), scratch.data_ptr(), sh)
+
+    warmup = min(args.warmup, 30)
+    steps = max(1, min(args.steps, 40))
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    got = (int(out.cpu().numpy().view(np.uint64)[0]), int(flags.cpu()[0]))
+    t0 = time.time()
+    acc, threads = oracle.exact_sum_binned(bits, "f64")
+    cpu_s = time.time() - t0
+    want = tuple(oracle.finish(acc, "f64"))
+    exact_val = struct.unpack("<d", struct.pack("<Q", want[0]))[0]
+    achieved = n * 8 / (ms * 1e-3) / 1e9
+    rec = {"metric": "exact FP64 sum Gelem/s + % HBM roofline (bit-exact), 2^31 elements with specials",
+           "value": round(n / (ms * 1e-3) / 1e9, 2), "unit": "Gelem/s", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "single exact sum, n=2^31 binary64 N(0,1)*2^k, k in "
+                                  "[-500,500], 0.1% subnormal/+-DBL_MAX (balanced)",
+                      "n": n, "seed": args.seed},
+           "bit_exact": got == want,
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": None}}
+    if not args.no_torch_sum:
+        xf = x.view(torch.float64)
+        for _ in range(3):
+            s = torch.sum(xf)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(steps):
+            s = torch.sum(xf)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        tms = ev0.elapsed_time(ev1) / steps
+        tval = float(s.cpu())
+        rec["torch_sum"] = {"ms_per_step": round(tms, 4),
+                            "gelem_s": round(n / (tms * 1e-3) / 1e9, 2),
+                            "value": tval, "exact_rounded": exact_val,
+                            "error_ulps": ulps_between(tval, exact_val)}
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = {"value": round(n / cpu_s / 1e9, 4), "unit": "Gelem/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": "the full n=2^31 input (exponent-binned 128-bit "
+                                         "C accumulation + big-int fold + RNE rounding)"}
+    print(json.dumps(rec), flush=True)
+
+
 def bench_segmented(args):
     """10^6 segments, lognormal lengths (median 256, sigma 2, clipped to
     [1, 2^20]), 50% binary64 / 37.5% binary32 / 12.5% bfloat16, replayed
@@ -289,6 +371,26 @@ def bench_segmented(args):
     xs.xsum_graph_destroy(graph)
     info = ss.info
     ss.close()
+    # the binary64 segments alone, same buffer and tuning, also one graph
+    f64_desc = desc[desc["dtype"] == 0]
+    f64_bytes = int(f64_desc["length"].sum()) * 8
+    ss64 = xs.SegmentedSum(f64_desc, tuning=autotune.tuning_struct(best))
+    out64 = torch.zeros(len(f64_desc), dtype=torch.int64, device="cuda")
+    fl64 = torch.zeros(len(f64_desc), dtype=torch.int32, device="cuda")
+    g64 = ss64.capture(dbuf, out64, fl64)
+    for _ in range(args.warmup):
+        xs.xsum_graph_launch(g64, sh)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        xs.xsum_graph_launch(g64, sh)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms64 = ev0.elapsed_time(ev1) / steps
+    same64 = np.array_equal(out64.cpu().numpy().view(np.uint64),
+                            res[desc["dtype"] == 0])
+    xs.xsum_graph_destroy(g64)
+    ss64.close()
     achieved = nbytes / (ms * 1e-3) / 1e9
     rec = {"metric": "segmented exact sums Gelem/s + % HBM roofline (bit-exact)",
            "value": round(nel / (ms * 1e-3) / 1e9, 2), "unit": "Gelem/s",
@@ -303,6 +405,11 @@ def bench_segmented(args):
            "plan_seconds": round(plan_s, 3), "autotune_seconds": round(tune_s, 1),
            "autotune": {"chosen": [list(best[0]), list(best[1]), best[2], best[3], best[4]],
                         "candidates_ms": [round(m, 4) for _, m in table]},
+           "f64_segments": {"segments": int(len(f64_desc)), "bytes": f64_bytes,
+                            "ms_per_step": round(ms64, 4),
+                            "gb_s": round(f64_bytes / (ms64 * 1e-3) / 1e9, 1),
+                            "frac": round(f64_bytes / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "same_bits_as_mixed_run": bool(same64)},
            "plan": {k: info[k] for k in
                                                        ("lane_segments", "wave_segments",
                                                         "chunked_segments", "work_items")},
