@@ -163,6 +163,36 @@ xsum_status_t xsum_acc_finalize(const xsum_acc_t *acc, int out_dtype,
                                 void *stream);
 
 /* ------------------------------------------------------------------------
+ * Inputs in host memory, larger than device memory if need be (Section 5:
+ * when the superaccumulator fits in internal memory, one scan that adds the
+ * inputs in any order gives the correctly rounded sum; here the device-
+ * resident exact state is the internal memory and the host array is read
+ * once, in chunks).
+ * ------------------------------------------------------------------------ */
+
+/* acc += the exact sum of n elements at x_host (host memory, pageable or
+ * pinned; pinned memory is copied at the full host-link rate).  The array is
+ * copied in chunks of chunk_bytes (0: 64 MiB; else a multiple of 16 in
+ * [4096, 2^34]) into two device staging buffers that alternate, on a copy
+ * stream of the call's own, while earlier chunks are added on `stream`.
+ * Returns once every chunk has been added (stream synchronised), so x_host
+ * may be reused at once.  The staging buffers (at most 2 x chunk_bytes of
+ * device memory) are allocated and freed by the call.  Errors: as
+ * xsum_acc_add, XSUM_ERANGE for a bad chunk_bytes, XSUM_ENOMEM if staging
+ * cannot be allocated. */
+xsum_status_t xsum_acc_add_host(xsum_acc_t *acc, const void *x_host, uint64_t n,
+                                int dtype, uint64_t chunk_bytes, void *stream);
+
+/* Exact sum of n elements in host memory, rounded once to out_dtype
+ * (XSUM_SAME: binary64 for binary64 input, else binary32), written to
+ * out_host (8, 4 or 2 bytes) with flags to flags_host (may be NULL).
+ * Blocking; allocates a 576-byte state plus the staging buffers of
+ * xsum_acc_add_host for the duration of the call. */
+xsum_status_t xsum_exact_sum_host(const void *x_host, uint64_t n, int dtype,
+                                  int out_dtype, void *out_host, uint32_t *flags_host,
+                                  uint64_t chunk_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Segmented sums: many independent exact sums of uneven lengths and mixed
  * formats in one persistent kernel launch (Section 6: each reducer sums its
  * own inputs into a superaccumulator; long inputs are summed per chunk and

@@ -29,6 +29,7 @@ EXPORTED = [
     "xsum_version", "xsum_last_error", "xsum_exact_sum", "xsum_exact_sum_f64",
     "xsum_exact_sum_async", "xsum_exact_sum_async_blocks", "xsum_acc_zero",
     "xsum_acc_add", "xsum_acc_merge", "xsum_acc_finalize",
+    "xsum_acc_add_host", "xsum_exact_sum_host",
     "xsum_segmented_plan", "xsum_plan_destroy", "xsum_plan_get_info",
     "xsum_segmented_workspace_size", "xsum_segmented_workspace_init",
     "xsum_segmented_run", "xsum_segmented_capture", "xsum_graph_launch",
@@ -124,6 +125,10 @@ def _load():
     lib.xsum_acc_merge.argtypes = [vp, vp, vp]
     lib.xsum_acc_finalize.restype = i32
     lib.xsum_acc_finalize.argtypes = [vp, i32, vp, vp, vp]
+    lib.xsum_acc_add_host.restype = i32
+    lib.xsum_acc_add_host.argtypes = [vp, vp, u64, i32, u64, vp]
+    lib.xsum_exact_sum_host.restype = i32
+    lib.xsum_exact_sum_host.argtypes = [vp, u64, i32, i32, vp, u32p, u64, vp]
     lib.xsum_segmented_plan.restype = i32
     lib.xsum_segmented_plan.argtypes = [vp, u64, i32, vp, ctypes.POINTER(vp)]
     lib.xsum_plan_destroy.restype = None
@@ -214,6 +219,39 @@ def xsum_acc_merge(dst, src, stream=0):
 def xsum_acc_finalize(acc, out_dtype, out, flags, stream=0):
     _check(_lib.xsum_acc_finalize(_p(acc), out_dtype, _p(out), _p(flags),
                                   _p(stream)))
+
+
+def xsum_acc_add_host(acc, x_host, n, dtype, chunk_bytes=0, stream=0):
+    _check(_lib.xsum_acc_add_host(_p(acc), _p(x_host), n, dtype, chunk_bytes,
+                                  _p(stream)))
+
+
+def xsum_exact_sum_host(x_host, n, dtype, out_dtype=SAME, chunk_bytes=0, stream=0):
+    """Blocking exact sum of n elements at host address x_host, streamed
+    through the device in chunks.  Returns (result bit pattern, flags)."""
+    out = ctypes.c_uint64(0)
+    flags = ctypes.c_uint32(0)
+    _check(_lib.xsum_exact_sum_host(_p(x_host), n, dtype, out_dtype, ctypes.byref(out),
+                                    ctypes.byref(flags), chunk_bytes, _p(stream)))
+    ob = OUT_BYTES[(F64 if dtype == F64 else F32) if out_dtype == SAME else out_dtype]
+    return out.value & ((1 << (8 * ob)) - 1), flags.value
+
+
+def exact_sum_host(array, dtype, out_dtype=SAME, chunk_bytes=0, stream=None):
+    """Blocking exact sum of a contiguous host array (numpy array or CPU
+    tensor; raw bit patterns are fine) of library dtype `dtype`.
+    Returns (result bit pattern, flags)."""
+    if hasattr(array, "data_ptr"):
+        if array.is_cuda or not array.is_contiguous():
+            raise ValueError("a contiguous CPU tensor is required")
+        ptr, nbytes = array.data_ptr(), array.numel() * array.element_size()
+    else:
+        if not array.flags["C_CONTIGUOUS"]:
+            raise ValueError("a C-contiguous array is required")
+        ptr, nbytes = array.ctypes.data, array.nbytes
+    n = nbytes // {F64: 8, F32: 4, BF16: 2}[dtype]
+    return xsum_exact_sum_host(ptr, n, dtype, out_dtype, chunk_bytes,
+                               stream_handle(stream) if stream is not None else 0)
 
 
 def xsum_segmented_plan(segs, out_dtype=SAME, tuning=None):

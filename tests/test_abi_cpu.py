@@ -119,3 +119,29 @@ def test_one_hip_runtime_whatever_the_import_order():
                        timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_host_streaming_arguments_are_checked_on_the_host(lib):
+    """xsum_exact_sum_host / xsum_acc_add_host reject bad arguments before
+    any device work (the checks run with no GPU present)."""
+    out = ctypes.c_uint64()
+    f = lib.xsum_exact_sum_host
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+    buf = (ctypes.c_double * 8)()
+    p = ctypes.addressof(buf)
+    assert f(p, 8, 7, 255, ctypes.addressof(out), None, 0, None) == 2       # input dtype
+    assert f(p, 8, 0, 9, ctypes.addressof(out), None, 0, None) == 2         # output dtype
+    assert f(None, 8, 0, 255, ctypes.addressof(out), None, 0, None) == 1    # NULL input
+    assert f(p + 4, 8, 0, 255, ctypes.addressof(out), None, 0, None) == 1   # misaligned
+    assert f(p, 8, 0, 255, None, None, 0, None) == 1                        # NULL out
+    for bad in (16, 4096 + 8, 1 << 35):                                     # chunk size
+        assert f(p, 8, 0, 255, ctypes.addressof(out), None, bad, None) == 5
+        assert "chunk_bytes" in _err(lib)
+    g = lib.xsum_acc_add_host
+    g.restype = ctypes.c_int
+    g.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                  ctypes.c_uint64, ctypes.c_void_p]
+    assert g(None, p, 8, 0, 0, None) == 1                                   # NULL state
+    assert g(ctypes.c_void_p(4096), p, 8, 3, 0, None) == 2                  # input dtype
