@@ -7,6 +7,8 @@ benchmark times (the library's persistent default grid).
 * n = 2^31 binary64 (16 GiB), N(0,1) * 2^k with subnormals and balanced
   +-DBL_MAX: exact result; with unbalanced +-DBL_MAX the sum overflows, and
   the exported exact state still equals the oracle's integer.
+* 10^6 segments of config 4 from one captured graph: sampled segments equal
+  the oracle's; all 10^6 results are identical across replays and plans.
 """
 
 import gc
@@ -88,4 +90,72 @@ def test_config3_full_size_overflow_state():
     digits = raw[:68 * 8].view(np.int64).tolist()
     assert sum(d << (32 * j) for j, d in enumerate(digits)) == acc.total
     del x
+    _release()
+
+
+SIZE = {0: 8, 1: 4, 2: 2}
+UINT = {0: np.uint64, 1: np.uint32, 2: np.uint16}
+NAMES = ["f64", "f32", "bf16"]
+
+
+def test_config4_full_size():
+    """10^6 segments (lognormal lengths, three formats, 10.9 GB) replayed from
+    one captured graph with the default plan, as the benchmark runs it:
+    sampled segments equal the oracle's one by one; every segment's bits are
+    the same on a second replay and under a plan that cuts the work
+    differently (more whole-wave items and many chunked segments)."""
+    import torch
+    import paper_1605_05436_amd as xs
+    print("config4 full size: 1e6 segments", flush=True)
+    buf, desc = workloads.config4(nseg=1_000_000, seed=0)
+    dbuf = torch.from_numpy(buf).to("cuda")
+    nseg = len(desc)
+    out = torch.zeros(nseg, dtype=torch.int64, device="cuda")
+    fl = torch.zeros(nseg, dtype=torch.int32, device="cuda")
+    ss = xs.SegmentedSum(desc)
+    graph = ss.capture(dbuf, out, fl)
+    results = []
+    try:
+        for _ in range(2):
+            out.fill_(-1)
+            fl.fill_(-1)
+            xs.xsum_graph_launch(graph, xs.stream_handle())
+            torch.cuda.synchronize()
+            results.append((out.cpu().numpy().view(np.uint64).copy(),
+                            fl.cpu().numpy().view(np.uint32).copy()))
+    finally:
+        xs.xsum_graph_destroy(graph)
+        ss.close()
+    assert np.array_equal(results[0][0], results[1][0])
+    assert np.array_equal(results[0][1], results[1][1])
+    res, rfl = results[0]
+    rng = np.random.default_rng(4)
+    idx = np.unique(np.concatenate([np.arange(0, nseg, 997),
+                                    np.argsort(desc["length"])[-50:],
+                                    rng.choice(nseg, 300, replace=False)]))
+    print("checking", len(idx), "sampled segments against the oracle", flush=True)
+    for i in idx.tolist():
+        o, L, d = int(desc["byte_offset"][i]), int(desc["length"][i]), int(desc["dtype"][i])
+        seg = buf[o:o + L * SIZE[d]].view(UINT[d])
+        if L > 50_000:
+            want = oracle.oracle_sum_binned(seg, NAMES[d], threads=8)
+        else:
+            want = oracle.oracle_sum(seg, NAMES[d])
+        assert (int(res[i]), int(rfl[i])) == tuple(want), (i, L, NAMES[d])
+    # a different cut of the same work
+    t = xs.SegTuning()
+    for d, (lm, wm) in enumerate(((1024, 1 << 16), (2048, 1 << 17), (4096, 1 << 18))):
+        t.lane_max[d] = lm
+        t.wave_max[d] = wm
+    t.chunk_vectors = 1 << 14
+    ss2 = xs.SegmentedSum(desc, tuning=t)
+    assert ss2.info["chunked_segments"] > 1000
+    out.fill_(-1)
+    fl.fill_(-1)
+    ss2.run(dbuf, out, fl)
+    torch.cuda.synchronize()
+    ss2.close()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), res)
+    assert np.array_equal(fl.cpu().numpy().view(np.uint32), rfl)
+    del dbuf, out, fl
     _release()
