@@ -563,85 +563,10 @@ static __device__ __forceinline__ uint64_t round_wave(int64_t a, int64_t b, int 
 
 // ------------------------------------------------- per-lane rounding --
 //
-// A lane that summed a whole segment in its own column rounds it alone: one
-// upward pass over the digits propagates the carries (sequentially, as the
-// paper's back-to-front carry scan of Section 5 step 4 does), and two trackers
-// follow the pass, one reading the digits as a non-negative number and one as
-// the magnitude of a negative number (two's complement: the +1 ripples
-// through low zero digits).  Each tracker keeps the highest non-zero digit,
-// the two digits below it and whether anything lower is non-zero, which is
-// all the rounding step needs.
-
-struct TopTracker {
-    int h = -1;
-    uint32_t w2 = 0, w1 = 0, w0 = 0;
-    bool sticky = false;
-    uint32_t p1 = 0, p2 = 0;
-    bool orlow = false;
-
-    __device__ __forceinline__ void feed(int d, uint32_t u)
-    {
-        if (u) {
-            h = d;
-            w2 = u;
-            w1 = p1;
-            w0 = p2;
-            sticky = orlow;
-        }
-        orlow = orlow || (p2 != 0);
-        p2 = p1;
-        p1 = u;
-    }
-};
-
-struct LaneFinisher {
-    int64_t carry = 0;
-    uint32_t neg_c = 1;       // +1 of the two's complement, still rippling
-    TopTracker pos, neg;
-    int next = 0;             // digit index of the next feed
-
-    // Feed the next raw digit (any int64 with |d| < 2^62).
-    __device__ __forceinline__ void feed(int64_t raw)
-    {
-        const int64_t x = raw + carry;
-        const uint32_t u = (uint32_t)((uint64_t)x & kLow32);
-        carry = x >> 32;
-        pos.feed(next, u);
-        const uint32_t m = (~u) + neg_c;   // (2^32 - 1 - u + c) mod 2^32
-        neg_c = neg_c && (u == 0);
-        neg.feed(next, m);
-        ++next;
-    }
-
-    // Round after the last digit; the remaining carry is the signed top.
-    // digit0 is the grid index of the first fed digit.
-    __device__ __forceinline__ uint64_t round(uint32_t special, int out_fmt,
-                                              int digit0, uint32_t &flags)
-    {
-        const OutFormat f = out_format(out_fmt);
-        flags = 0;
-        uint64_t bits;
-        if (special_result(special, f, bits, flags))
-            return bits;
-        const int64_t top = carry;
-        const bool negative = top < 0;
-        if (!(top == 0 || top == -1) || (negative && neg.h < 0)) {
-            flags = XSUM_FLAG_OVERFLOW | XSUM_FLAG_INEXACT;
-            return fmt_inf(f, negative);
-        }
-        // select by value (a reference chosen at run time would force both
-        // trackers into memory)
-        const int h = negative ? neg.h : pos.h;
-        if (h < 0)
-            return 0;                                // exact zero -> +0
-        const uint32_t w2 = negative ? neg.w2 : pos.w2;
-        const uint32_t w1 = negative ? neg.w1 : pos.w1;
-        const uint32_t w0 = negative ? neg.w0 : pos.w0;
-        const bool sticky = negative ? neg.sticky : pos.sticky;
-        return round_magnitude(negative, digit0 + h, w2, w1, w0, sticky, f,
-                               flags);
-    }
-};
+// A lane that summed a whole segment in its own column rounds it alone, with
+// no help from other lanes: a sequential scan carries the signed digits
+// upward (Section 5, step 4: a scan that propagates the signed carries) and
+// the most significant non-zero digits are rounded (step 5).
 
 // Two-pass rounding of one lane's digits (digit d of the lane is at
 // col[d * 64], weight 2^(32 (digit0 + d)) in units of 2^-1074), used when a

@@ -3,8 +3,9 @@
 // reducer sums its own numbers into a superaccumulator; long inputs are first
 // combined per chunk and the per-chunk states merged and rounded once).
 //
-// Work items come from a host-built plan, popped by every wave from a shared
-// queue (one device atomic per item):
+// Work items come from a host-built plan, longest first, claimed by every
+// wave from a shared queue (one device atomic per large item, one per few
+// short items):
 //   * lane group: up to 64 whole segments of one format and similar length
 //     (the plan sorts segments by length).  Each lane streams its own segment
 //     into its private LDS column exactly as the single-sum kernel does, then

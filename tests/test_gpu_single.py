@@ -123,3 +123,41 @@ def test_set_equality_reduction():
     D[17] = 63 if D[17] != 63 else 62
     bits, _ = workloads.set_equality(C, D)
     assert gpu_sum(bits, "f64") == want(bits, "f64")
+
+
+def test_graph_capture_replays_match_eager():
+    """The asynchronous sum captured in a graph (its scratch state returns to
+    zero after every launch and no memset node is recorded) gives the eager
+    result on every replay, with eager library work and synchronisations
+    between the replays."""
+    import torch
+    import paper_1605_05436_amd as xs
+    bits = workloads.family("anderson", 3_000_001, 2000, seed=12)
+    expect = want(bits, "f64")
+    x = to_device(bits)
+    other = workloads.family("mixed", 100_003, 200, seed=13)
+    xo = to_device(other)
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    st = xs.new_states(1)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        xs.xsum_exact_sum_async(x.data_ptr(), len(bits), xs.F64, xs.F64, out.data_ptr(),
+                                fl.data_ptr(), st.data_ptr(), xs.stream_handle(s))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        xs.xsum_exact_sum_async(x.data_ptr(), len(bits), xs.F64, xs.F64, out.data_ptr(),
+                                fl.data_ptr(), st.data_ptr(), xs.stream_handle(s))
+    for rep in range(4):
+        out.fill_(0)
+        fl.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (int(out.cpu().numpy().view(np.uint64)[0]), int(fl.cpu()[0]))
+        assert got == expect, rep
+        assert st.cpu().numpy().tobytes() == bytes(576)
+        # eager work on another stream and tensor between the replays
+        assert xs.exact_sum(xo, xs.F64) == want(other, "f64")
