@@ -163,6 +163,38 @@ xsum_status_t xsum_acc_finalize(const xsum_acc_t *acc, int out_dtype,
                                 void *stream);
 
 /* ------------------------------------------------------------------------
+ * Compact encoding of a state (host code only; no device is touched), for
+ * checkpoints and for exchanging states between processes (Section 2: a
+ * sparse superaccumulator stores only its non-zero components, each with its
+ * exponent).  The value is carry-normalised (Section 3, step 6) and written
+ * as sign and magnitude; the magnitude is stored as the run of radix-2^32
+ * digits from its lowest to its highest non-zero digit.  Little-endian
+ * layout: u32 magic 0x31535358 ("XSS1"), u32 special bits, u8 sign (1 =
+ * negative), u8 index of the run's first digit (digit j weighs
+ * 2^(32 j - 1074)), u8 digit count c, u8 0, then c u32 digits, lowest first:
+ * 12 + 4 c bytes, at most XSUM_STATE_ENCODED_MAX.  An all-zero state is the
+ * 12-byte header with c = 0.
+ * ------------------------------------------------------------------------ */
+#define XSUM_STATE_ENCODED_MAX 292
+
+/* Encode a state held in host memory (copy it from the device first; a
+ * state copied after any completed xsum call is valid).  Digits may be in any
+ * form with |digit| <= 2^62; the value's normalised top digit must lie in
+ * [-2^61, 2^61] (every sum of at most 2^31 finite inputs does).  *len
+ * receives the encoded size; XSUM_ERANGE if cap is smaller (or buf NULL),
+ * with *len still set.  XSUM_EINVAL for NULL acc/len or unknown special bits. */
+xsum_status_t xsum_state_encode(const xsum_acc_t *acc, void *buf, size_t cap,
+                                size_t *len);
+
+/* Decode into a host state in canonical form (digits 0..66 in [0, 2^32), the
+ * signed top digit, special bits, ticket and padding zero); copy it to the
+ * device to use it, e.g. as the source of xsum_acc_merge.  XSUM_EINVAL for a
+ * wrong magic, length, header field or a digit run that does not start and
+ * end with non-zero digits; XSUM_ERANGE for a value outside the encodable
+ * range. */
+xsum_status_t xsum_state_decode(const void *buf, size_t len, xsum_acc_t *acc);
+
+/* ------------------------------------------------------------------------
  * Inputs in host memory, larger than device memory if need be (Section 5:
  * when the superaccumulator fits in internal memory, one scan that adds the
  * inputs in any order gives the correctly rounded sum; here the device-

@@ -29,7 +29,8 @@ EXPORTED = [
     "xsum_version", "xsum_last_error", "xsum_exact_sum", "xsum_exact_sum_f64",
     "xsum_exact_sum_async", "xsum_exact_sum_async_blocks", "xsum_acc_zero",
     "xsum_acc_add", "xsum_acc_merge", "xsum_acc_finalize",
-    "xsum_acc_add_host", "xsum_exact_sum_host",
+    "xsum_acc_add_host", "xsum_exact_sum_host", "xsum_state_encode",
+    "xsum_state_decode",
     "xsum_segmented_plan", "xsum_plan_destroy", "xsum_plan_get_info",
     "xsum_segmented_workspace_size", "xsum_segmented_workspace_init",
     "xsum_segmented_run", "xsum_segmented_capture", "xsum_graph_launch",
@@ -129,6 +130,10 @@ def _load():
     lib.xsum_acc_add_host.argtypes = [vp, vp, u64, i32, u64, vp]
     lib.xsum_exact_sum_host.restype = i32
     lib.xsum_exact_sum_host.argtypes = [vp, u64, i32, i32, vp, u32p, u64, vp]
+    lib.xsum_state_encode.restype = i32
+    lib.xsum_state_encode.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    lib.xsum_state_decode.restype = i32
+    lib.xsum_state_decode.argtypes = [vp, ctypes.c_size_t, vp]
     lib.xsum_segmented_plan.restype = i32
     lib.xsum_segmented_plan.argtypes = [vp, u64, i32, vp, ctypes.POINTER(vp)]
     lib.xsum_plan_destroy.restype = None
@@ -252,6 +257,32 @@ def exact_sum_host(array, dtype, out_dtype=SAME, chunk_bytes=0, stream=None):
     n = nbytes // {F64: 8, F32: 4, BF16: 2}[dtype]
     return xsum_exact_sum_host(ptr, n, dtype, out_dtype, chunk_bytes,
                                stream_handle(stream) if stream is not None else 0)
+
+
+STATE_ENCODED_MAX = 292
+
+
+def xsum_state_encode(state):
+    """Compact encoding (bytes) of one exact state given as 576 host bytes
+    (bytes, bytearray or a uint8 numpy array / CPU tensor)."""
+    import numpy as np
+    a = np.ascontiguousarray(np.frombuffer(bytes(state), dtype=np.uint8)
+                             if isinstance(state, (bytes, bytearray))
+                             else np.asarray(state, dtype=np.uint8).reshape(-1))
+    if a.size != STATE_BYTES:
+        raise ValueError("a state is %d bytes" % STATE_BYTES)
+    buf = ctypes.create_string_buffer(STATE_ENCODED_MAX)
+    n = ctypes.c_size_t(0)
+    _check(_lib.xsum_state_encode(a.ctypes.data, buf, STATE_ENCODED_MAX, ctypes.byref(n)))
+    return buf.raw[:n.value]
+
+
+def xsum_state_decode(data):
+    """576-byte canonical state (bytes) from an encoding."""
+    data = bytes(data)
+    out = ctypes.create_string_buffer(STATE_BYTES)
+    _check(_lib.xsum_state_decode(data, len(data), out))
+    return out.raw
 
 
 def xsum_segmented_plan(segs, out_dtype=SAME, tuning=None):

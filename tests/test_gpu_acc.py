@@ -127,3 +127,42 @@ def test_zero_resets_many_states():
     torch.cuda.synchronize()
     assert not sts.cpu().numpy().any()
     del keep
+
+
+def _read_encoding(data):
+    """Reader of the encoded-state layout documented in include/xsum.h."""
+    import struct
+    magic, special, sign, lo, cnt, zero = struct.unpack_from("<IIBBBB", data, 0)
+    assert magic == 0x31535358 and zero == 0 and len(data) == 12 + 4 * cnt
+    mag = sum(d << (32 * (lo + k))
+              for k, d in enumerate(struct.unpack_from("<%dI" % cnt, data, 12)))
+    return special, -mag if sign else mag
+
+
+def test_encoded_device_state_equals_oracle_and_merges_back():
+    """A state built on the device, copied to the host and encoded, holds the
+    oracle's exact integer; decoded and copied back to the device it merges
+    into another state, and the merged state rounds to the oracle's sum of
+    both inputs."""
+    import torch
+    import paper_1605_05436_amd as xs
+    a = workloads.family("anderson", 700_001, 2000, seed=41)
+    b = workloads.config3(n=500_000, seed=42)
+    b_unbal = workloads.config3(n=500_000, seed=43, balanced=False)
+    for first, second in ((a, b), (b, a), (a, b_unbal)):
+        st = xs.new_states(2)
+        keep = [_add(st[0], first, "f64"), _add(st[1], second, "f64")]
+        torch.cuda.synchronize()
+        raw = st[0].cpu().numpy().tobytes()
+        enc = xs.xsum_state_encode(raw)
+        acc, _ = oracle.exact_sum_binned(first, "f64")
+        assert _read_encoding(enc) == (0, acc.total)
+        dec = xs.xsum_state_decode(enc)
+        moved = torch.from_numpy(np.frombuffer(dec, dtype=np.uint8).copy()).to("cuda")
+        xs.xsum_acc_merge(st[1].data_ptr(), moved.data_ptr(), xs.stream_handle())
+        torch.cuda.synchronize()
+        both = np.concatenate([first, second])
+        want = oracle.oracle_sum_binned(both, "f64")
+        assert _finalize(st[1], "f64") == tuple(want)
+        assert _state_int(st[1])[0] == oracle.exact_sum_binned(both, "f64")[0].total
+        del keep
