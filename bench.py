@@ -73,10 +73,13 @@ def measured_traffic(n, sources=KERNEL_SOURCES, profile=TRAFFIC_PROFILE, match=N
     return None
 
 
-def time_oracle(bits, fmt, budget_s=3.0):
-    """Run the oracle's binned sum over the whole input repeatedly for about
-    budget_s seconds (at least once); returns (acc, threads, median seconds
-    per run, runs)."""
+def cpu_baseline_full(bits, fmt, terms=None, budget_s=3.0):
+    """The cpu_baseline leg for one large sum: the oracle's binned sum over
+    the whole input, repeated for about budget_s seconds (at least once), then
+    rounded.  With terms, also checks the workload's closed form (the exact
+    total equals the sum of terms).  Returns ((bits, flags), closed form holds,
+    threads, median seconds per run, runs); the bench compares the GPU's bits
+    with this result."""
     import oracle
     times = []
     acc = threads = None
@@ -86,7 +89,20 @@ def time_oracle(bits, fmt, budget_s=3.0):
         acc, threads = oracle.exact_sum_binned(bits, fmt)
         times.append(time.time() - t0)
     times.sort()
-    return acc, threads, times[len(times) // 2], len(times)
+    want = tuple(oracle.finish(acc, fmt))
+    closed = terms is None or oracle.exact_sum_binned(terms, fmt)[0].total == acc.total
+    return want, closed, threads, times[len(times) // 2], len(times)
+
+
+def cpu_baseline_sample(pieces, threads=16):
+    """The cpu_baseline leg for many sums: the oracle on a bounded sample of
+    (bit-pattern array, format) pieces, timed.  Returns (results, elements,
+    seconds, threads); the bench also checks the GPU's bits against them."""
+    import oracle
+    t0 = time.time()
+    results = [tuple(oracle.oracle_sum_binned(b, fmt, threads=threads)) for b, fmt in pieces]
+    secs = time.time() - t0
+    return results, sum(len(b) for b, _ in pieces), secs, threads
 
 
 def ulps_between(a, b):
@@ -174,12 +190,9 @@ def main():
 
     # parity of the timed result against the oracle (closed form: the sum of
     # the replaced pairs equals the sum of everything)
-    import oracle
-    acc, threads, cpu_s, cpu_runs = time_oracle(bits, "f64")
-    want_bits, want_flags = oracle.finish(acc, "f64")
-    closed = oracle.exact_sum_binned(terms, "f64")[0].total
-    bit_exact = (result_bits, result_flags) == (want_bits, want_flags) and \
-        closed == acc.total
+    (want_bits, want_flags), closed, threads, cpu_s, cpu_runs = \
+        cpu_baseline_full(bits, "f64", terms)
+    bit_exact = (result_bits, result_flags) == (want_bits, want_flags) and closed
     exact_val = struct.unpack("<d", struct.pack("<Q", want_bits))[0]
     log("oracle: %.3f s per run (median of %d) on %d threads, bit_exact=%s"
         % (cpu_s, cpu_runs, threads, bit_exact))
@@ -253,7 +266,6 @@ def bench_config3(args):
     import torch
     import paper_1605_05436_amd as xs
     import workloads
-    import oracle
 
     n = 1 << 31
     t0 = time.time()
@@ -284,8 +296,7 @@ def bench_config3(args):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
     got = (int(out.cpu().numpy().view(np.uint64)[0]), int(flags.cpu()[0]))
-    acc, threads, cpu_s, cpu_runs = time_oracle(bits, "f64")
-    want = tuple(oracle.finish(acc, "f64"))
+    want, _, threads, cpu_s, cpu_runs = cpu_baseline_full(bits, "f64")
     exact_val = struct.unpack("<d", struct.pack("<Q", want[0]))[0]
     achieved = n * 8 / (ms * 1e-3) / 1e9
     rec = {"metric": "exact FP64 sum Gelem/s + % HBM roofline (bit-exact), 2^31 elements with specials",
@@ -332,7 +343,6 @@ def bench_segmented(args):
     import torch
     import paper_1605_05436_amd as xs
     import workloads
-    import oracle
 
     t0 = time.time()
     buf, desc = workloads.config4(nseg=args.nseg, seed=args.seed)
@@ -376,12 +386,12 @@ def bench_segmented(args):
                                     np.argsort(desc["length"])[-50:]]))
     names = ["f64", "f32", "bf16"]
     uint = [np.uint64, np.uint32, np.uint16]
-    ok = True
+    pieces = []
     for i in idx.tolist():
         o, L, d = int(desc["byte_offset"][i]), int(desc["length"][i]), int(desc["dtype"][i])
-        seg = buf[o:o + L * [8, 4, 2][d]].view(uint[d])
-        w = oracle.oracle_sum_binned(seg, names[d], threads=16)
-        ok = ok and (int(res[i]), int(rf[i])) == tuple(w)
+        pieces.append((buf[o:o + L * [8, 4, 2][d]].view(uint[d]), names[d]))
+    wants, cpu_elems, cpu_s, cpu_threads = cpu_baseline_sample(pieces)
+    ok = all((int(res[i]), int(rf[i])) == w for i, w in zip(idx.tolist(), wants))
     xs.xsum_graph_destroy(graph)
     info = ss.info
     ss.close()
@@ -416,6 +426,10 @@ def bench_segmented(args):
                       "segments": len(desc), "elements": nel, "bytes": nbytes,
                       "seed": args.seed},
            "bit_exact_sample": ok, "sample_segments": int(len(idx)),
+           "cpu_baseline": {"value": round(cpu_elems / cpu_s / 1e9, 4), "unit": "Gelem/s",
+                            "cores": cpu_threads, "kind": "oracle",
+                            "sample": "%d sampled segments (every 997th and the 50 longest, "
+                                      "%d elements), one oracle sum each" % (len(idx), cpu_elems)},
            "plan_seconds": round(plan_s, 3), "autotune_seconds": round(tune_s, 1),
            "autotune": {"chosen": [list(best[0]), list(best[1]), best[2], best[3], best[4]],
                         "candidates_ms": [round(m, 4) for _, m in table]},
@@ -443,7 +457,6 @@ def bench_serving(args):
     copied into the server's arena on admission."""
     import torch
     import workloads
-    import oracle
     from paper_1605_05436_amd.serve import ExactSumServer, Request, run_trace, latency_stats
 
     t0 = time.time()
@@ -477,12 +490,11 @@ def bench_serving(args):
     # parity on a sample of requests
     sample = rng.choice(len(reqs), size=min(200, len(reqs)), replace=False)
     byid = {r.rid: r for r in done}
-    ok = True
-    for i in sample.tolist():
-        r = reqs[i]
-        fmt = "f64" if r.dtype == 0 else "f32"
-        w = oracle.oracle_sum_binned(host[r.dtype][offs[i]:offs[i] + r.n], fmt, threads=16)
-        ok = ok and (byid[r.rid].bits, byid[r.rid].flags) == tuple(w)
+    pieces = [(host[reqs[i].dtype][offs[i]:offs[i] + reqs[i].n],
+               "f64" if reqs[i].dtype == 0 else "f32") for i in sample.tolist()]
+    wants, cpu_elems, cpu_s, cpu_threads = cpu_baseline_sample(pieces)
+    ok = all((byid[reqs[i].rid].bits, byid[reqs[i].rid].flags) == w
+             for i, w in zip(sample.tolist(), wants))
     elems = float(sum(r.n for r in done))
     rec = {"metric": "exact-sum serving: aggregate Gelem/s with p50/p99 latency (bit-exact)",
            "value": round(elems / wall / 1e9, 3), "unit": "Gelem/s", "n_gpus": 1,
@@ -497,7 +509,11 @@ def bench_serving(args):
            if srv.gpu_time_ms else None,
            "gpu_busy_fraction": round(srv.gpu_time_ms * 1e-3 / wall, 4),
            "batches": srv.batches, "bit_exact_sample": ok,
-           "sample_requests": int(len(sample))}
+           "sample_requests": int(len(sample)),
+           "cpu_baseline": {"value": round(cpu_elems / cpu_s / 1e9, 4), "unit": "Gelem/s",
+                            "cores": cpu_threads, "kind": "oracle",
+                            "sample": "%d sampled requests (%d elements), one oracle sum each"
+                                      % (len(sample), cpu_elems)}}
     print(json.dumps(rec), flush=True)
 
 
