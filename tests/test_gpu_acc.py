@@ -166,3 +166,102 @@ def test_encoded_device_state_equals_oracle_and_merges_back():
         assert _finalize(st[1], "f64") == tuple(want)
         assert _state_int(st[1])[0] == oracle.exact_sum_binned(both, "f64")[0].total
         del keep
+
+
+def _canonical_digits(value):
+    return [(value >> (32 * j)) & 0xFFFFFFFF for j in range(67)] + [value >> (32 * 67)]
+
+
+def _scramble(digits, rng, moves):
+    """Same value, non-canonical digits: move multiples of 2^32 between
+    neighbours (d[j] += c 2^32, d[j+1] -= c), staying within |d| < 2^62."""
+    d = list(digits)
+    for _ in range(moves):
+        j = rng.randrange(0, 67)
+        c = rng.randrange(-(1 << 28), (1 << 28) + 1)
+        if abs(d[j] + (c << 32)) < (1 << 61) and abs(d[j + 1] - c) < (1 << 61):
+            d[j] += c << 32
+            d[j + 1] -= c
+    return d
+
+
+def test_raw_digit_vectors_normalise_and_round():
+    """Finalize and merge of states written directly with adversarial digit
+    vectors (carry and borrow chains through many digits, non-canonical
+    digits, ties, binade edges, subnormal and overflow boundaries): the
+    rounded result equals the oracle's rounding of the state's integer in
+    every output format, and a merge leaves the canonical digits."""
+    import random
+    import torch
+    import paper_1605_05436_amd as xs
+    rng = random.Random(11)
+    M = (1 << 32) - 1
+    values = []
+    cases = [
+        [M] * 40 + [0] * 28,                         # 2^1280 - 1: ripples on rounding
+        [M] * 66 + [0, 0],
+        [-1] + [0] * 67,                             # -2^-1074
+        [0] * 20 + [-1] + [0] * 47,
+        [1] + [0] * 20 + [-1] + [0] * 46,            # borrow through 20 digits
+        [0] * 67 + [-1],
+        [1] + [0] * 66 + [-1],                       # -(2^2144 - 1): beyond every format
+        [0] * 68,
+    ]
+    for d in cases:
+        values.append((d, sum(v << (32 * j) for j, v in enumerate(d))))
+    # ties and near-ties of binary64 / binary32 / bfloat16 at random scales
+    for _ in range(150):
+        prec = rng.choice([53, 24, 8])
+        q = rng.randrange(0, 1900)
+        m = rng.randrange(1 << (prec - 1), 1 << prec)
+        # 41 bits below the significand: half an ulp, just below, just above
+        tail = rng.choice([1 << 40, (1 << 40) - 1, (1 << 40) + 1, 0, 1]) << q
+        v = (m << (q + 41)) + tail
+        v = -v if rng.random() < 0.5 else v
+        values.append((_scramble(_canonical_digits(v), rng, 30), v))
+    # overflow and subnormal edges
+    for v in ((1 << 2098) - (1 << 2044), (1 << 2098) - (1 << 2044) - 1, (1 << 52) - 1,
+              1 << 52, (1 << 2098) - (1 << 2045)):
+        for s in (1, -1):
+            values.append((_scramble(_canonical_digits(s * v), rng, 30), s * v))
+    # random raw digits
+    for _ in range(100):
+        d = [rng.randrange(-(1 << 61), (1 << 61) + 1) for _ in range(67)]
+        d.append(rng.randrange(-3, 4))
+        values.append((d, sum(v << (32 * j) for j, v in enumerate(d))))
+    raw = np.zeros((len(values), 576), dtype=np.uint8)
+    for i, (d, _) in enumerate(values):
+        raw[i, :544] = np.array(d, dtype=np.int64).view(np.uint8)
+    st = torch.from_numpy(raw).to("cuda")
+    for i, (d, v) in enumerate(values):
+        for fmt in ("f64", "f32", "bf16"):
+            assert _finalize(st[i], fmt) == tuple(oracle.round_to_format(v, fmt)), (i, fmt)
+    merged = xs.new_states(len(values))
+    for i in range(len(values)):
+        xs.xsum_acc_merge(merged[i].data_ptr(), st[i].data_ptr(), xs.stream_handle())
+    torch.cuda.synchronize()
+    got = merged.cpu().numpy()[:, :544].copy().view(np.int64)
+    for i, (d, v) in enumerate(values):
+        assert got[i].tolist() == _canonical_digits(v), i
+
+
+def test_checkpoint_and_resume_through_the_encoding():
+    """Stop a long sum after some chunks, keep only the encoded state (as a
+    checkpoint would), resume into a fresh state and finish: same bits as the
+    uninterrupted sum and the oracle."""
+    import torch
+    import paper_1605_05436_amd as xs
+    bits, _ = workloads.config2(log2n=21, seed=9)
+    cut = 777_777
+    st = xs.new_states(1)
+    keep = _add(st, bits[:cut], "f64")
+    torch.cuda.synchronize()
+    ckpt = xs.xsum_state_encode(st.cpu().numpy().tobytes())
+    del st, keep
+    resumed = torch.from_numpy(np.frombuffer(xs.xsum_state_decode(ckpt),
+                                             dtype=np.uint8).copy()).to("cuda")
+    keep = _add(resumed, bits[cut:], "f64")
+    torch.cuda.synchronize()
+    want = oracle.finish(oracle.exact_sum_binned(bits, "f64")[0], "f64")
+    assert _finalize(resumed, "f64") == tuple(want)
+    del keep
