@@ -124,7 +124,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-torch-sum", action="store_true")
     ap.add_argument("--workload", default="single",
-                    choices=["single", "config3", "segmented", "serving"])
+                    choices=["single", "config1", "config3", "segmented", "serving"])
     ap.add_argument("--nseg", type=int, default=1_000_000)
     ap.add_argument("--duration", type=float, default=60.0)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -144,6 +144,8 @@ def main():
         return bench_segmented(args)
     if args.workload == "config3":
         return bench_config3(args)
+    if args.workload == "config1":
+        return bench_config1(args)
     if args.workload == "serving":
         return bench_serving(args)
 
@@ -256,6 +258,90 @@ def main():
                                "sample": "the full n=2^28 input, median of %d runs "
                                          "(exponent-binned 128-bit C accumulation + "
                                          "big-int fold + RNE rounding)" % cpu_runs}
+    print(json.dumps(rec), flush=True)
+
+
+def bench_config1(args):
+    """10^6 binary64 values, exponents in [-50, 50] (8 MB): small enough to
+    stay in the 256 MB last-level cache, so a sum is bound by launch and
+    finish latency.  Warm: one captured graph of 100 back-to-back sums,
+    replayed.  Cold: a 1 GiB buffer is rewritten before each single sum, and
+    only the sum is timed."""
+    import torch
+    import paper_1605_05436_amd as xs
+    import workloads
+
+    n = 1_000_000
+    bits = workloads.config1(n, seed=args.seed)
+    x = torch.from_numpy(bits.view(np.int64)).to("cuda")
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    scratch = xs.new_states(1)
+    s = torch.cuda.Stream()
+    sh = xs.stream_handle(s)
+
+    def one():
+        xs.xsum_exact_sum_async(x.data_ptr(), n, xs.F64, xs.F64, out.data_ptr(),
+                                flags.data_ptr(), scratch.data_ptr(), sh)
+
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(10):
+            one()
+    torch.cuda.synchronize()
+    per_graph = 100
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(per_graph):
+            one()
+    replays = max(1, args.steps // 10)
+    with torch.cuda.stream(s):
+        for _ in range(max(1, args.warmup // 10)):
+            g.replay()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(s)
+        for _ in range(replays):
+            g.replay()
+        ev1.record(s)
+    torch.cuda.synchronize()
+    warm_us = ev0.elapsed_time(ev1) * 1e3 / (replays * per_graph)
+    got_warm = (int(out.cpu().numpy().view(np.uint64)[0]), int(flags.cpu()[0]))
+    # cold: evict the input from the caches before every timed sum
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    cold = []
+    with torch.cuda.stream(s):
+        for i in range(30):
+            flush.fill_(i & 0xff)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            one()
+            e1.record(s)
+            e1.synchronize()
+            cold.append(e0.elapsed_time(e1) * 1e3)
+    cold.sort()
+    cold_us = cold[len(cold) // 2]
+    got = (int(out.cpu().numpy().view(np.uint64)[0]), int(flags.cpu()[0]))
+    want, _, threads, cpu_s, cpu_runs = cpu_baseline_full(bits, "f64")
+    rec = {"metric": "exact FP64 sum Gelem/s (bit-exact), 10^6 elements, graph-replayed",
+           "value": round(n / (warm_us * 1e-6) / 1e9, 2), "unit": "Gelem/s", "n_gpus": 1,
+           "steps": replays * per_graph, "warmup": max(1, args.warmup // 10) * per_graph,
+           "ms_per_step": round(warm_us * 1e-3, 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "single exact sum, n=10^6 binary64, exponents in [-50, 50]",
+                      "n": n, "seed": args.seed},
+           "bit_exact": got == want and got_warm == want,
+           "warm_us_per_sum": round(warm_us, 2), "cold_us_per_sum": round(cold_us, 2),
+           "cold_gelem_s": round(n / (cold_us * 1e-6) / 1e9, 2),
+           "roofline": {"bound": "latency", "achieved": round(n * 8 / (warm_us * 1e-6) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(n * 8 / (warm_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": None},
+           "cpu_baseline": {"value": round(n / cpu_s / 1e9, 4), "unit": "Gelem/s",
+                            "cores": threads, "kind": "oracle",
+                            "sample": "the full 10^6 input, median of %d runs" % cpu_runs}}
     print(json.dumps(rec), flush=True)
 
 
