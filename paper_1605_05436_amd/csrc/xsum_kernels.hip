@@ -263,8 +263,19 @@ static hipError_t launch_fmt(const void *x, uint64_t n, xsum_acc_t *acc,
     const uint64_t tail = rest - nvec * G::kPerVec;
     const uint64_t tile = (uint64_t)S::kWaves * 64 * S::kUnroll;
     const uint64_t tiles = (nvec + tile - 1) / tile;
-    uint64_t blocks = shape.blocks > 0 ? (uint64_t)shape.blocks
-                                       : (uint64_t)persistent_blocks(FMT, cu_count);
+    uint64_t blocks;
+    if (shape.blocks > 0) {
+        blocks = (uint64_t)shape.blocks;
+    } else {
+        // Every block pays a fixed merge, a device-scope fence and a ticket,
+        // so a small input gets about one block per 64 KiB (at least 32
+        // blocks to keep the loads spread), a large one the persistent grid.
+        constexpr uint64_t kVectorsPerBlock = 4096, kMinBlocks = 32;
+        blocks = (uint64_t)persistent_blocks(FMT, cu_count);
+        const uint64_t want = (nvec + kVectorsPerBlock - 1) / kVectorsPerBlock;
+        if (want < blocks)
+            blocks = want > kMinBlocks ? want : kMinBlocks;
+    }
     if (blocks > tiles)
         blocks = tiles;
     if (blocks < 1)
