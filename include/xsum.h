@@ -243,10 +243,10 @@ typedef struct xsum_segment {
 
 /* Tuning knobs of a plan, indexed by dtype d where per-format; 0 in any
  * field means the library default.
- *   lane_max[d]   segments with at most this many elements are summed one per
- *                 lane, 64 to a wave (default 4096 / 8192 / 16384 for
- *                 binary64 / binary32 / bfloat16: 32 KiB of input; at most
- *                 2^20 / 2^22 / 2^23)
+ *   lane_max[d]   segments with at most this many elements are summed by a
+ *                 few lanes each, 16 to 64 segments to a wave (default 8192 /
+ *                 16384 / 32768 for binary64 / binary32 / bfloat16: 64 KiB of
+ *                 input; at most 2^20 / 2^22 / 2^23)
  *   wave_max[d]   longer segments with at most this many elements are summed
  *                 whole by one wave (default: 4 MiB of input)
  *   chunk_vectors longer segments still are cut into chunks of this many

@@ -27,13 +27,13 @@ from . import (SegTuning, SegmentedSum, xsum_graph_launch, xsum_graph_destroy,
 DEFAULT_CANDIDATES = [
     # (lane_max per dtype, wave_max per dtype, chunk_vectors, blocks_per_cu, lane_buckets)
     ((0, 0, 0), (0, 0, 0), 0, 0, 0),                       # library defaults
-    ((2048, 4096, 8192), (0, 0, 0), 0, 0, 4),
-    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 4),
-    ((4096, 8192, 16384), (0, 0, 0), 0, 0, 2),
-    ((4096, 8192, 16384), (0, 0, 0), 0, 0, 8),
-    ((4096, 8192, 16384), (1 << 18, 1 << 19, 1 << 20), 1 << 17, 0, 4),
-    ((4096, 8192, 16384), (1 << 20, 1 << 21, 1 << 22), 1 << 19, 0, 4),
-    ((4096, 8192, 16384), (0, 0, 0), 0, 3, 4),
+    ((4096, 8192, 16384), (0, 0, 0), 0, 0, 4),
+    ((16384, 32768, 65536), (0, 0, 0), 0, 0, 4),
+    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 2),
+    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 8),
+    ((8192, 16384, 32768), (1 << 18, 1 << 19, 1 << 20), 1 << 17, 0, 4),
+    ((8192, 16384, 32768), (1 << 20, 1 << 21, 1 << 22), 1 << 19, 0, 4),
+    ((8192, 16384, 32768), (0, 0, 0), 0, 3, 4),
 ]
 
 

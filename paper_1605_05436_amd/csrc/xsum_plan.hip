@@ -55,7 +55,9 @@ constexpr int kPerVec[3] = {2, 4, 8};
 constexpr int kBytes[3] = {8, 4, 2};
 // Default per-lane limits: segments up to this many elements are summed one
 // per lane (64 KiB of input per lane).
-constexpr uint64_t kLaneMaxDefault[3] = {4096, 8192, 16384};
+constexpr uint64_t kLaneMaxDefault[3] = {8192, 16384, 32768};
+// segment sizes (bytes) from which lane groups give a segment two or four lanes
+constexpr uint64_t kTwoLanesFrom = 1024, kFourLanesFrom = 8192;
 // Segments up to 4 MiB are summed whole by one wave.
 constexpr uint64_t kWaveMaxDefault[3] = {1ull << 19, 1ull << 20, 1ull << 21};
 
@@ -209,19 +211,25 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
                 return bx > by;
             return segs[x].byte_offset < segs[y].byte_offset;
         });
-        for (size_t g = 0; g < ids.size(); g += 64) {
-            const size_t cnt = std::min<size_t>(64, ids.size() - g);
+        for (size_t g = 0; g < ids.size();) {
+            // lanes per segment: one for short segments (the per-group
+            // rounding is then shared by 64 segments), two or four for longer
+            // ones, whose loads then touch fewer, longer runs of memory
+            const uint64_t bytes0 = segs[ids[g]].length * kBytes[dt];
+            const uint32_t glog = bytes0 < kTwoLanesFrom ? 0 : bytes0 < kFourLanesFrom ? 1 : 2;
+            const size_t cnt = std::min<size_t>(64u >> glog, ids.size() - g);
             HostTask h{};
-            h.t.kind_dtype_flags = xsum::kLaneGroup | ((uint32_t)dt << 8);
+            h.t.kind_dtype_flags = xsum::kLaneGroup | ((uint32_t)dt << 8) | (glog << 16);
             h.t.a = (uint32_t)lanes.size();
             h.t.b = (uint32_t)cnt;
             uint64_t maxlen = 0;
             for (size_t k = g; k < g + cnt; ++k)
                 maxlen = std::max<uint64_t>(maxlen, segs[ids[k]].length);
-            h.cost = maxlen / kPerVec[dt] + 1;
+            h.cost = (maxlen / kPerVec[dt] >> glog) + 1;
             tasks.push_back(h);
             for (size_t k = g; k < g + cnt; ++k)
                 lanes.push_back({segs[ids[k]].byte_offset, (uint32_t)segs[ids[k]].length, ids[k]});
+            g += cnt;
         }
     }
     // longest work first, so the queue drains evenly

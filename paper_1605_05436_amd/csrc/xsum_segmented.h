@@ -24,12 +24,14 @@ enum SegChunkFlags : uint32_t {
     kChunkFirst = 1,  // also adds the segment's unaligned head elements
     kChunkLast = 2,   // also adds the segment's ragged tail elements
 };
+// A lane group's flags field is log2 of the lanes that share each segment
+// (0, 1 or 2: 64, 32 or 16 segments per group).
 
 // 32-byte work item.
 struct SegTask {
-    uint32_t kind_dtype_flags;  // kind | dtype << 8 | chunk flags << 16
+    uint32_t kind_dtype_flags;  // kind | dtype << 8 | flags << 16
     uint32_t a;                 // lane group: first lane entry; else: segment
-    uint32_t b;                 // lane group: lane count;  chunk: state slot
+    uint32_t b;                 // lane group: segment count;  chunk: state slot
     uint32_t nchunks;           // chunk: chunks of its segment
     uint64_t v0;                // whole: byte offset;  chunk: first 16-byte vector
     uint64_t nv;                // whole: elements;     chunk: vectors in the chunk

@@ -129,14 +129,21 @@ __device__ __forceinline__ uint64_t finish_lane(uint64_t *col, uint32_t spec,
     }
 }
 
-// One lane group: lane l < count sums the segment of its lane entry e.
+// One lane group: 2^glog lanes share each segment (64 >> glog segments, the
+// first `count` valid).  Lane l reads every 2^glog-th 16-byte vector of
+// segment l >> glog, starting at vector l mod 2^glog, into its own column, so
+// a load instruction touches 64 >> glog runs of 2^glog contiguous vectors
+// instead of 64 scattered ones.  The columns of a segment's lanes are then
+// carry-normalised, summed into its first lane's column, and rounded there.
 template <int FMT, int UL>
 __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLane &e,
-                                               uint32_t count, uint64_t *col, int out_mode,
+                                               uint32_t count, uint32_t glog,
+                                               uint64_t *col, int out_mode,
                                                uint64_t *out, uint32_t *flags, int lane)
 {
     using G = Geo<FMT>;
-    const bool live = (uint32_t)lane < count;
+    const uint32_t sub = (uint32_t)lane & ((1u << glog) - 1);
+    const bool live = ((uint32_t)lane >> glog) < count;
     const uint32_t s = e.seg;
     const uint64_t off = live ? e.byte_offset : 0;
     const uint64_t L = live ? e.length : 0;
@@ -146,24 +153,26 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
         head = L;
     const uint64_t nv = (L - head) / G::kPerVec;
     const uint64_t tail = L - head - nv * G::kPerVec;
-    const vec4u *vp = (const vec4u *)(p + head * G::kBytes);
+    const vec4u *vp = (const vec4u *)(p + head * G::kBytes) + sub;
+    // this lane's vectors: sub, sub + 2^glog, ...
+    const uint64_t my_nv = nv > sub ? ((nv - sub - 1) >> glog) + 1 : 0;
     uint32_t spec = 0;
 
-    const uint64_t my_iters = (nv + UL - 1) / UL;
+    const uint64_t my_iters = (my_nv + UL - 1) / UL;
     const uint32_t iters = wave_max_u32((uint32_t)my_iters);
     // binary64: at most 1024 + 2*UL + 2 elements between normalisations
     constexpr int kNormIters = 512 / UL;
     int since = 0;
-    // each lane walks its own segment, UL vectors per step, the next step's
-    // loads in flight while the current step is added
+    // each lane walks its share of its segment, UL vectors per step, the next
+    // step's loads in flight while the current step is added
     vec4u qa[UL], qb[UL];
     auto load_step = [&](vec4u (&q)[UL], uint32_t it) {
 #pragma unroll
         for (int j = 0; j < UL; ++j) {
             const uint64_t i = (uint64_t)it * UL + j;
             q[j] = vec4u{0u, 0u, 0u, 0u};
-            if (i < nv)
-                q[j] = vp[i];   // cached: a lane's UL loads share its lines
+            if (i < my_nv)
+                q[j] = vp[i << glog];   // cached: neighbouring loads share lines
         }
     };
     auto norm_step = [&]() {
@@ -188,16 +197,42 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
         add_tile<FMT, UL>(qb, col, spec);
         norm_step();
     }
-    for (uint64_t i = 0; i < head; ++i)
-        add_scalar<FMT>(p + i * G::kBytes, col, spec);
-    const uint8_t *tp = p + head * G::kBytes + nv * 16;
-    for (uint64_t i = 0; i < tail; ++i)
-        add_scalar<FMT>(tp + i * G::kBytes, col, spec);
+    if (sub == 0) {
+        for (uint64_t i = 0; i < head; ++i)
+            add_scalar<FMT>(p + i * G::kBytes, col, spec);
+        const uint8_t *tp = p + head * G::kBytes + nv * 16;
+        for (uint64_t i = 0; i < tail; ++i)
+            add_scalar<FMT>(tp + i * G::kBytes, col, spec);
+    }
+    if (glog > 0) {
+        // the segment's lanes are neighbours: fold their columns into the
+        // first one.  Binary64 columns are carry-normalised first (entries
+        // below 2^32, the last one holding only carries), so a sum of up to
+        // four entries cannot overflow; binary32 bins hold at most lane_max
+        // chunks below 2^31 each.
+        for (uint32_t k = 1; k < (1u << glog); k <<= 1)
+            spec |= (uint32_t)__shfl_xor((int)spec, (int)k, 64);
+        if constexpr (FMT == XSUM_F64)
+            normalise_column<G::kN>(col);
+        wave_lds_fence();
+        if (sub == 0) {
+#pragma unroll
+            for (int d = 0; d < G::kN; ++d) {
+                int64_t v = (int64_t)lds_load(col + d * 64);
+                for (uint32_t k = 1; k < (1u << glog); ++k)
+                    v += (int64_t)lds_load(col + d * 64 + k);
+                lds_store(col + d * 64, (uint64_t)v);
+            }
+        }
+        wave_lds_fence();
+    }
 
     const int of = out_mode == XSUM_SAME ? LaneOut<FMT>::kNatural : out_mode;
     uint32_t fl;
+    // every lane rounds (and clears) its own column; only a segment's first
+    // lane holds the whole sum and writes it
     const uint64_t bits = finish_lane<FMT>(col, spec, of, fl);
-    if (live) {
+    if (live && sub == 0) {
         out[s] = bits;
         if (flags)
             flags[s] = fl;
@@ -377,15 +412,16 @@ __device__ __forceinline__ void run_chunk(const uint8_t *base, const SegDesc *se
     }
 }
 
-// The lane entry of work item t for this lane (zero when t is not a lane
-// group or the lane is past its count).
+// The lane entry of work item t for this lane: that of its segment, lane
+// >> glog (zero when t is not a lane group or the segment is past its count).
 __device__ __forceinline__ SegLane lane_entry(const SegLane *__restrict__ lanes,
                                               const SegTask &t, uint32_t ntasks_left,
                                               int lane)
 {
     SegLane e{0, 0, 0};
-    if (ntasks_left && (t.kind_dtype_flags & 0xffu) == kLaneGroup && (uint32_t)lane < t.b)
-        e = lanes[t.a + lane];
+    const uint32_t seg = (uint32_t)lane >> (t.kind_dtype_flags >> 16);
+    if (ntasks_left && (t.kind_dtype_flags & 0xffu) == kLaneGroup && seg < t.b)
+        e = lanes[t.a + seg];
     return e;
 }
 
@@ -454,12 +490,13 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
         const uint32_t kind = t.kind_dtype_flags & 0xffu;
         const uint32_t dtype = (t.kind_dtype_flags >> 8) & 0xffu;
         if (kind == kLaneGroup) {
+            const uint32_t glog = t.kind_dtype_flags >> 16;
             if (dtype == XSUM_F64)
-                run_lane_group<XSUM_F64, UL>(base, e, t.b, col, out_mode, out, flags, lane);
+                run_lane_group<XSUM_F64, UL>(base, e, t.b, glog, col, out_mode, out, flags, lane);
             else if (dtype == XSUM_F32)
-                run_lane_group<XSUM_F32, UL>(base, e, t.b, col, out_mode, out, flags, lane);
+                run_lane_group<XSUM_F32, UL>(base, e, t.b, glog, col, out_mode, out, flags, lane);
             else
-                run_lane_group<XSUM_BF16, UL>(base, e, t.b, col, out_mode, out, flags, lane);
+                run_lane_group<XSUM_BF16, UL>(base, e, t.b, glog, col, out_mode, out, flags, lane);
         } else if (kind == kWhole) {
             if (dtype == XSUM_F64)
                 run_whole<XSUM_F64, UC>(base, t, w, col, out_mode, out, flags, lane);
