@@ -129,6 +129,22 @@ __device__ __forceinline__ uint64_t finish_lane(uint64_t *col, uint32_t spec,
     }
 }
 
+// Add the entries of the NL - 1 columns to the right of this lane's into its
+// own.  Every read is independent, so the rows are unrolled and the reads
+// issued in batches.
+template <int N, int NL>
+__device__ __forceinline__ void fold_columns(uint64_t *col)
+{
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+        int64_t v = (int64_t)lds_load(col + d * 64);
+#pragma unroll
+        for (int k = 1; k < NL; ++k)
+            v += (int64_t)lds_load(col + d * 64 + k);
+        lds_store(col + d * 64, (uint64_t)v);
+    }
+}
+
 // One lane group: 2^glog lanes share each segment (64 >> glog segments, the
 // first `count` valid).  Lane l reads every 2^glog-th 16-byte vector of
 // segment l >> glog, starting at vector l mod 2^glog, into its own column, so
@@ -216,13 +232,10 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
             normalise_column<G::kN>(col);
         wave_lds_fence();
         if (sub == 0) {
-#pragma unroll
-            for (int d = 0; d < G::kN; ++d) {
-                int64_t v = (int64_t)lds_load(col + d * 64);
-                for (uint32_t k = 1; k < (1u << glog); ++k)
-                    v += (int64_t)lds_load(col + d * 64 + k);
-                lds_store(col + d * 64, (uint64_t)v);
-            }
+            if (glog == 1)
+                fold_columns<G::kN, 2>(col);
+            else
+                fold_columns<G::kN, 4>(col);
         }
         wave_lds_fence();
     }
