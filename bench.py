@@ -517,7 +517,7 @@ def bench_segmented(args):
                             "sample": "%d sampled segments (every 997th and the 50 longest, "
                                       "%d elements), one oracle sum each" % (len(idx), cpu_elems)},
            "plan_seconds": round(plan_s, 3), "autotune_seconds": round(tune_s, 1),
-           "autotune": {"chosen": [list(best[0]), list(best[1]), best[2], best[3], best[4]],
+           "autotune": {"chosen": [list(best[0]), list(best[1])] + list(best[2:]),
                         "candidates_ms": [round(m, 4) for _, m in table]},
            "f64_segments": {"segments": int(len(f64_desc)), "bytes": f64_bytes,
                             "ms_per_step": round(ms64, 4),
@@ -531,8 +531,7 @@ def bench_segmented(args):
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                         "traffic": measured_traffic(
                             nel, SEG_KERNEL_SOURCES, SEG_TRAFFIC_PROFILE,
-                            {"tuning": [list(best[0]), list(best[1]), best[2], best[3],
-                                        best[4]]})}}
+                            {"tuning": [list(best[0]), list(best[1])] + list(best[2:])})}}
     print(json.dumps(rec), flush=True)
 
 

@@ -256,13 +256,19 @@ typedef struct xsum_segment {
  *                 range [1, 16])
  *   lane_buckets  per-lane segments are grouped by length in this many
  *                 buckets per doubling (default 4, at most 64) and taken in
- *                 buffer order inside a bucket */
+ *                 buffer order inside a bucket
+ *   two_lanes_from, four_lanes_from
+ *                 segment sizes in bytes from which a segment summed in a lane
+ *                 group gets two, then four lanes (default 2048 and 32768;
+ *                 four_lanes_from below two_lanes_from is XSUM_ERANGE) */
 typedef struct xsum_seg_tuning {
     uint64_t lane_max[3];
     uint64_t wave_max[3];
     uint64_t chunk_vectors;
     uint32_t blocks_per_cu;
     uint32_t lane_buckets;
+    uint64_t two_lanes_from;
+    uint64_t four_lanes_from;
 } xsum_seg_tuning_t;
 
 /* Plan statistics. */

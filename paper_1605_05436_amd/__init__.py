@@ -49,7 +49,8 @@ class SegTuning(ctypes.Structure):
     """xsum_seg_tuning_t (0 = library default in every field)."""
     _fields_ = [("lane_max", ctypes.c_uint64 * 3), ("wave_max", ctypes.c_uint64 * 3),
                 ("chunk_vectors", ctypes.c_uint64),
-                ("blocks_per_cu", ctypes.c_uint32), ("lane_buckets", ctypes.c_uint32)]
+                ("blocks_per_cu", ctypes.c_uint32), ("lane_buckets", ctypes.c_uint32),
+                ("two_lanes_from", ctypes.c_uint64), ("four_lanes_from", ctypes.c_uint64)]
 
 
 class PlanInfo(ctypes.Structure):

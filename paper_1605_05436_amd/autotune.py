@@ -25,15 +25,18 @@ from . import (SegTuning, SegmentedSum, xsum_graph_launch, xsum_graph_destroy,
                stream_handle)
 
 DEFAULT_CANDIDATES = [
-    # (lane_max per dtype, wave_max per dtype, chunk_vectors, blocks_per_cu, lane_buckets)
-    ((0, 0, 0), (0, 0, 0), 0, 0, 0),                       # library defaults
-    ((4096, 8192, 16384), (0, 0, 0), 0, 0, 4),
-    ((16384, 32768, 65536), (0, 0, 0), 0, 0, 4),
-    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 2),
-    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 8),
-    ((8192, 16384, 32768), (1 << 18, 1 << 19, 1 << 20), 1 << 17, 0, 4),
-    ((8192, 16384, 32768), (1 << 20, 1 << 21, 1 << 22), 1 << 19, 0, 4),
-    ((8192, 16384, 32768), (0, 0, 0), 0, 3, 4),
+    # (lane_max per dtype, wave_max per dtype, chunk_vectors, blocks_per_cu,
+    #  lane_buckets, two_lanes_from, four_lanes_from); 0 = library default
+    ((0, 0, 0), (0, 0, 0), 0, 0, 0, 0, 0),                  # library defaults
+    ((4096, 8192, 16384), (0, 0, 0), 0, 0, 4, 0, 0),
+    ((16384, 32768, 65536), (0, 0, 0), 0, 0, 4, 0, 0),
+    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 2, 0, 0),
+    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 8, 0, 0),
+    ((8192, 16384, 32768), (1 << 18, 1 << 19, 1 << 20), 1 << 17, 0, 4, 0, 0),
+    ((8192, 16384, 32768), (1 << 20, 1 << 21, 1 << 22), 1 << 19, 0, 4, 0, 0),
+    ((8192, 16384, 32768), (0, 0, 0), 0, 3, 4, 0, 0),
+    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 4, 1024, 8192),
+    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 4, 4096, 1 << 40),
 ]
 
 
@@ -67,7 +70,8 @@ def batch_signature(desc):
 
 
 def _tuning(c):
-    lane, wave, chunk, bpc, buckets = c
+    lane, wave, chunk, bpc, buckets = c[:5]
+    two, four = c[5:7] if len(c) >= 7 else (0, 0)
     t = SegTuning()
     for d in range(3):
         t.lane_max[d] = lane[d]
@@ -75,7 +79,17 @@ def _tuning(c):
     t.chunk_vectors = chunk
     t.blocks_per_cu = bpc
     t.lane_buckets = buckets
+    t.two_lanes_from = two
+    t.four_lanes_from = four
     return t
+
+
+def _as_list(c):
+    return [list(c[0]), list(c[1])] + list(c[2:])
+
+
+def _from_list(c):
+    return (tuple(c[0]), tuple(c[1])) + tuple(c[2:])
 
 
 def _time_candidate(desc, dbuf, cand, reps, out, flags):
@@ -119,8 +133,7 @@ def tune_segmented(desc, dbuf, candidates=None, reps=5, use_cache=True,
         except (OSError, ValueError):
             cache = {}
         if sig in cache:
-            c = cache[sig]["tuning"]
-            return (tuple(c[0]), tuple(c[1]), c[2], c[3], c[4]), cache[sig]["table"]
+            return _from_list(cache[sig]["tuning"]), cache[sig]["table"]
     cands = candidates or DEFAULT_CANDIDATES
     out = torch.zeros(len(desc), dtype=torch.int64, device="cuda")
     flags = torch.zeros(len(desc), dtype=torch.int32, device="cuda")
@@ -137,9 +150,8 @@ def tune_segmented(desc, dbuf, candidates=None, reps=5, use_cache=True,
         if best is None or ms < best[1] * (1.0 - margin):
             best = (cand, ms)
     if use_cache:
-        cache[sig] = {"tuning": [list(best[0][0]), list(best[0][1]), best[0][2],
-                                 best[0][3], best[0][4]],
-                      "table": [[list(map(list, c[:2])) + list(c[2:]), m] for c, m in table],
+        cache[sig] = {"tuning": _as_list(best[0]),
+                      "table": [[_as_list(c), m] for c, m in table],
                       "arch": _arch(), "time": time.time()}
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -57,7 +57,7 @@ constexpr int kBytes[3] = {8, 4, 2};
 // per lane (64 KiB of input per lane).
 constexpr uint64_t kLaneMaxDefault[3] = {8192, 16384, 32768};
 // segment sizes (bytes) from which lane groups give a segment two or four lanes
-constexpr uint64_t kTwoLanesFrom = 1024, kFourLanesFrom = 8192;
+constexpr uint64_t kTwoLanesFromDefault = 2048, kFourLanesFromDefault = 32768;
 // Segments up to 4 MiB are summed whole by one wave.
 constexpr uint64_t kWaveMaxDefault[3] = {1ull << 19, 1ull << 20, 1ull << 21};
 
@@ -100,7 +100,14 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
     uint64_t chunk_vectors = xsum::segmented_chunk_vectors();
     int blocks_per_cu = 0;
     int lane_buckets = 4;
+    uint64_t two_lanes_from = kTwoLanesFromDefault, four_lanes_from = kFourLanesFromDefault;
     if (tuning) {
+        if (tuning->two_lanes_from)
+            two_lanes_from = tuning->two_lanes_from;
+        if (tuning->four_lanes_from)
+            four_lanes_from = tuning->four_lanes_from;
+        if (four_lanes_from < two_lanes_from)
+            return api_fail(XSUM_ERANGE, "four_lanes_from below two_lanes_from");
         if (tuning->lane_buckets)
             lane_buckets = (int)tuning->lane_buckets;
         if (lane_buckets > 64)
@@ -216,7 +223,7 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
             // rounding is then shared by 64 segments), two or four for longer
             // ones, whose loads then touch fewer, longer runs of memory
             const uint64_t bytes0 = segs[ids[g]].length * kBytes[dt];
-            const uint32_t glog = bytes0 < kTwoLanesFrom ? 0 : bytes0 < kFourLanesFrom ? 1 : 2;
+            const uint32_t glog = bytes0 < two_lanes_from ? 0 : bytes0 < four_lanes_from ? 1 : 2;
             const size_t cnt = std::min<size_t>(64u >> glog, ids.size() - g);
             HostTask h{};
             h.t.kind_dtype_flags = xsum::kLaneGroup | ((uint32_t)dt << 8) | (glog << 16);

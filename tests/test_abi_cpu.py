@@ -145,3 +145,44 @@ def test_host_streaming_arguments_are_checked_on_the_host(lib):
                   ctypes.c_uint64, ctypes.c_void_p]
     assert g(None, p, 8, 0, 0, None) == 1                                   # NULL state
     assert g(ctypes.c_void_p(4096), p, 8, 3, 0, None) == 2                  # input dtype
+
+
+def test_python_structs_match_the_header_layout(tmp_path):
+    """The binding's ctypes/numpy mirrors of the public structs have the
+    sizes and field offsets the C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    import numpy as np
+    import paper_1605_05436_amd as xs
+    import workloads
+    if shutil.which("gcc") is None:
+        pytest.skip("no host compiler")
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "xsum.h"
+int main(void) {
+    printf("%zu %zu %zu %zu %zu %zu\n", sizeof(xsum_acc_t), sizeof(xsum_segment_t),
+           sizeof(xsum_seg_tuning_t), sizeof(xsum_plan_info_t), sizeof(xsum_batch_item_t),
+           offsetof(xsum_seg_tuning_t, two_lanes_from));
+    printf("%zu %zu %zu\n", offsetof(xsum_seg_tuning_t, blocks_per_cu),
+           offsetof(xsum_plan_info_t, workspace_bytes), offsetof(xsum_batch_item_t, first_task));
+    return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I" + os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    a, b = subprocess.run([str(exe)], capture_output=True, text=True,
+                          check=True).stdout.split("\n")[:2]
+    acc, seg, tun, info, item, two = map(int, a.split())
+    bpc, wsb, first = map(int, b.split())
+    assert acc == xs.STATE_BYTES
+    assert seg == workloads.SEGMENT_DTYPE.itemsize
+    assert tun == ctypes.sizeof(xs.SegTuning) and two == xs.SegTuning.two_lanes_from.offset
+    assert bpc == xs.SegTuning.blocks_per_cu.offset
+    assert info == ctypes.sizeof(xs.PlanInfo) and wsb == xs.PlanInfo.workspace_bytes.offset
+    dt = xs.batch_item_dtype()
+    assert item == dt.itemsize and first == dt.fields["first_task"][1]
+    assert isinstance(np.dtype(dt), np.dtype)
