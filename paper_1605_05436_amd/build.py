@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libxsum.so")
 SOURCES = ["xsum_kernels.hip", "xsum_segmented.hip", "xsum_plan.hip", "xsum_api.hip",
            "xsum_stream.hip", "xsum_state.hip"]
-HEADERS = ["xsum_device.h", "xsum_internal.h", "xsum_segmented.h"]
+HEADERS = ["xsum_device.h", "xsum_internal.h", "xsum_segmented.h", "xsum_host.h"]
 ARCH = os.environ.get("XSUM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

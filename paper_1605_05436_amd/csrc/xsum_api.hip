@@ -11,6 +11,7 @@
 
 #include "xsum.h"
 #include "xsum_internal.h"
+#include "xsum_host.h"
 
 namespace {
 
@@ -47,14 +48,8 @@ std::map<std::pair<int, void *>, BlockingWs *> g_ws;
 
 bool valid_in(int d) { return d == XSUM_F64 || d == XSUM_F32 || d == XSUM_BF16; }
 
-int resolve_out(int dtype, int out)
-{
-    if (out == XSUM_SAME)
-        return dtype == XSUM_F64 ? XSUM_F64 : XSUM_F32;
-    return out;
-}
-
-int out_bytes(int out) { return out == XSUM_F64 ? 8 : out == XSUM_F32 ? 4 : 2; }
+using xsum::out_bytes;
+using xsum::resolve_out;
 
 xsum_status_t check_input(const void *x, uint64_t n, int dtype)
 {

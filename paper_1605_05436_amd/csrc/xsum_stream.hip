@@ -15,6 +15,7 @@
 
 #include "xsum.h"
 #include "xsum_internal.h"
+#include "xsum_host.h"
 
 namespace xsum {
 xsum_status_t api_fail(xsum_status_t st, const std::string &msg);
@@ -134,13 +135,6 @@ xsum_status_t add_host(xsum_acc_t *acc, const void *x, uint64_t n, int dtype,
     return e == hipSuccess ? XSUM_OK : api_hip_fail(e, "hipStreamSynchronize");
 }
 
-int resolve_out(int dtype, int out)
-{
-    if (out == XSUM_SAME)
-        return dtype == XSUM_F64 ? XSUM_F64 : XSUM_F32;
-    return out;
-}
-
 }  // namespace
 
 extern "C" {
@@ -165,7 +159,7 @@ xsum_status_t xsum_exact_sum_host(const void *x_host, uint64_t n, int dtype,
     xsum_status_t st = check_host_args(x_host, n, dtype, chunk_bytes);
     if (st != XSUM_OK)
         return st;
-    const int of = resolve_out(dtype, out_dtype);
+    const int of = xsum::resolve_out(dtype, out_dtype);
     if (of != XSUM_F64 && of != XSUM_F32 && of != XSUM_BF16)
         return api_fail(XSUM_EDTYPE, "unknown output dtype " + std::to_string(out_dtype));
     hipStream_t s = (hipStream_t)stream;
@@ -200,7 +194,7 @@ xsum_status_t xsum_exact_sum_host(const void *x_host, uint64_t n, int dtype,
     (void)hipFree(dev_out);
     if (st != XSUM_OK)
         return st;
-    std::memcpy(out_host, host_out, (size_t)(of == XSUM_F64 ? 8 : of == XSUM_F32 ? 4 : 2));
+    std::memcpy(out_host, host_out, (size_t)xsum::out_bytes(of));
     if (flags_host)
         std::memcpy(flags_host, host_out + 8, 4);
     return XSUM_OK;
