@@ -77,9 +77,12 @@ def cpu_baseline_full(bits, fmt, terms=None, budget_s=3.0):
     """The cpu_baseline leg for one large sum: the oracle's binned sum over
     the whole input, repeated for about budget_s seconds (at least once), then
     rounded.  With terms, also checks the workload's closed form (the exact
-    total equals the sum of terms).  Returns ((bits, flags), closed form holds,
-    threads, median seconds per run, runs); the bench compares the GPU's bits
-    with this result."""
+    total equals the sum of terms).  Also gives log10 of the condition number
+    sum|x| / |sum x| from one more exact sum over the magnitudes (None for an
+    exact zero).  Returns ((bits, flags), closed form holds, threads, median
+    seconds per run, runs, log10 condition number); the bench compares the
+    GPU's bits with this result."""
+    import math
     import oracle
     times = []
     acc = threads = None
@@ -91,7 +94,11 @@ def cpu_baseline_full(bits, fmt, terms=None, budget_s=3.0):
     times.sort()
     want = tuple(oracle.finish(acc, fmt))
     closed = terms is None or oracle.exact_sum_binned(terms, fmt)[0].total == acc.total
-    return want, closed, threads, times[len(times) // 2], len(times)
+    sign_bit = {"f64": np.uint64(1 << 63), "f32": np.uint32(1 << 31),
+                "bf16": np.uint16(1 << 15)}[fmt]
+    mag = oracle.exact_sum_binned(bits & ~sign_bit, fmt)[0].total
+    cond = None if acc.total == 0 else round(math.log10(mag) - math.log10(abs(acc.total)), 2)
+    return want, closed, threads, times[len(times) // 2], len(times), cond
 
 
 def cpu_baseline_sample(pieces, threads=16):
@@ -192,7 +199,7 @@ def main():
 
     # parity of the timed result against the oracle (closed form: the sum of
     # the replaced pairs equals the sum of everything)
-    (want_bits, want_flags), closed, threads, cpu_s, cpu_runs = \
+    (want_bits, want_flags), closed, threads, cpu_s, cpu_runs, log10_cond = \
         cpu_baseline_full(bits, "f64", terms)
     bit_exact = (result_bits, result_flags) == (want_bits, want_flags) and closed
     exact_val = struct.unpack("<d", struct.pack("<Q", want_bits))[0]
@@ -241,6 +248,7 @@ def main():
                             "gelem_s": round(n / (tms * 1e-3) / 1e9, 2),
                             "value": tval, "exact_rounded": exact_val,
                             "error_ulps": ulps_between(tval, exact_val),
+                            "log10_condition_number": log10_cond,
                             "rel_error": (abs(tval - exact_val) / abs(exact_val)
                                           if exact_val else None)}
 
@@ -324,7 +332,7 @@ def bench_config1(args):
     cold.sort()
     cold_us = cold[len(cold) // 2]
     got = (int(out.cpu().numpy().view(np.uint64)[0]), int(flags.cpu()[0]))
-    want, _, threads, cpu_s, cpu_runs = cpu_baseline_full(bits, "f64")
+    want, _, threads, cpu_s, cpu_runs, log10_cond = cpu_baseline_full(bits, "f64")
     rec = {"metric": "exact FP64 sum Gelem/s (bit-exact), 10^6 elements, graph-replayed",
            "value": round(n / (warm_us * 1e-6) / 1e9, 2), "unit": "Gelem/s", "n_gpus": 1,
            "steps": replays * per_graph, "warmup": max(1, args.warmup // 10) * per_graph,
@@ -382,7 +390,7 @@ def bench_config3(args):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
     got = (int(out.cpu().numpy().view(np.uint64)[0]), int(flags.cpu()[0]))
-    want, _, threads, cpu_s, cpu_runs = cpu_baseline_full(bits, "f64")
+    want, _, threads, cpu_s, cpu_runs, log10_cond = cpu_baseline_full(bits, "f64")
     exact_val = struct.unpack("<d", struct.pack("<Q", want[0]))[0]
     achieved = n * 8 / (ms * 1e-3) / 1e9
     rec = {"metric": "exact FP64 sum Gelem/s + % HBM roofline (bit-exact), 2^31 elements with specials",
@@ -412,7 +420,8 @@ def bench_config3(args):
         rec["torch_sum"] = {"ms_per_step": round(tms, 4),
                             "gelem_s": round(n / (tms * 1e-3) / 1e9, 2),
                             "value": tval, "exact_rounded": exact_val,
-                            "error_ulps": ulps_between(tval, exact_val)}
+                            "error_ulps": ulps_between(tval, exact_val),
+                            "log10_condition_number": log10_cond}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = {"value": round(n / cpu_s / 1e9, 4), "unit": "Gelem/s",
                                "cores": threads, "kind": "oracle",
