@@ -173,3 +173,69 @@ def test_autotuner_picks_a_candidate_with_identical_results(tmp_path, monkeypatc
     want = expected(buf, desc)
     results, _ = run_gpu(buf, desc, tuning=autotune.tuning_struct(best))
     assert np.array_equal(results[0][0], want[0]) and np.array_equal(results[0][1], want[1])
+
+
+def test_empty_plans_run_and_capture():
+    """No segments, and only empty segments: runs and captured graphs work;
+    an empty segment sums to +0."""
+    import torch
+    import paper_1605_05436_amd as xs
+    dbuf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    empty = np.zeros(0, dtype=workloads.SEGMENT_DTYPE)
+    ss = xs.SegmentedSum(empty)
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ss.run(dbuf, out)
+    g = ss.capture(dbuf, out)
+    xs.xsum_graph_launch(g, xs.stream_handle())
+    torch.cuda.synchronize()
+    xs.xsum_graph_destroy(g)
+    ss.close()
+    zeros = np.zeros(300, dtype=workloads.SEGMENT_DTYPE)
+    zeros["dtype"] = np.arange(300) % 3
+    ss = xs.SegmentedSum(zeros)
+    out = torch.full((300,), -1, dtype=torch.int64, device="cuda")
+    fl = torch.full((300,), -1, dtype=torch.int32, device="cuda")
+    g = ss.capture(dbuf, out, fl)
+    for _ in range(3):
+        out.fill_(-1)
+        fl.fill_(-1)
+        xs.xsum_graph_launch(g, xs.stream_handle())
+        torch.cuda.synchronize()
+        assert not out.cpu().numpy().any() and not fl.cpu().numpy().any()
+    xs.xsum_graph_destroy(g)
+    ss.close()
+
+
+def test_all_chunked_plan_replays():
+    """Every segment cut into chunks (per-segment states and tickets): three
+    graph replays and an eager run in between give the oracle's bits each
+    time, so the states and tickets return to zero after every launch."""
+    import torch
+    import paper_1605_05436_amd as xs
+    buf, desc = workloads.config4(nseg=400, seed=8)
+    want = expected(buf, desc)
+    t = xs.SegTuning()
+    for d in range(3):
+        t.lane_max[d] = 1
+        t.wave_max[d] = 1
+    t.chunk_vectors = 64 * 3
+    dbuf = torch.from_numpy(buf).to("cuda")
+    ss = xs.SegmentedSum(desc, tuning=t)
+    assert ss.info["chunked_segments"] == int((desc["length"] > 1).sum())
+    out = torch.zeros(len(desc), dtype=torch.int64, device="cuda")
+    fl = torch.zeros(len(desc), dtype=torch.int32, device="cuda")
+    g = ss.capture(dbuf, out, fl)
+    try:
+        for rep in range(3):
+            out.fill_(0)
+            fl.fill_(0)
+            xs.xsum_graph_launch(g, xs.stream_handle())
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), want[0]), rep
+            assert np.array_equal(fl.cpu().numpy().view(np.uint32), want[1]), rep
+            ss.run(dbuf, out, fl)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), want[0]), rep
+    finally:
+        xs.xsum_graph_destroy(g)
+        ss.close()
