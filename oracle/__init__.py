@@ -21,6 +21,14 @@ Floating-Point Numbers"):
 
 Nothing here follows the paper's parallel algorithms; the oracle is the plain
 definition, written out.
+
+Parity unpinned by the paper: the conventions it leaves open, which the
+oracle fixes in ``exact.finish`` and ``ieee.round_to_format``: a finite sum
+that rounds past the largest finite value gives an infinity with an overflow
+flag; NaN and infinity inputs give what IEEE 754 addition gives; an exact zero
+gives +0; the output format defaults to binary64 for binary64 input and
+binary32 otherwise.  These are checked against IEEE 754 arithmetic (CPython
+floats, numpy, torch) and for self-consistency, not against the paper.
 """
 
 from .ieee import (FORMATS, UNIT_EXP, FLAG_INEXACT, FLAG_OVERFLOW, FLAG_NAN,
