@@ -45,6 +45,9 @@ KERNEL_SOURCES = ["paper_1605_05436_amd/csrc/xsum_kernels.hip",
                   "paper_1605_05436_amd/csrc/xsum_device.h",
                   "paper_1605_05436_amd/csrc/xsum_internal.h"]
 TRAFFIC_PROFILE = "profiles/accumulate_f64_n2e28_hbm_counters.md"
+TRAFFIC_PROFILES = {"f64": TRAFFIC_PROFILE,
+                    "f32": "profiles/accumulate_f32_n2e29_hbm_counters.md",
+                    "bf16": "profiles/accumulate_bf16_n2e30_hbm_counters.md"}
 SEG_KERNEL_SOURCES = ["paper_1605_05436_amd/csrc/xsum_segmented.hip",
                       "paper_1605_05436_amd/csrc/xsum_segmented.h",
                       "paper_1605_05436_amd/csrc/xsum_plan.hip",
@@ -92,7 +95,7 @@ def cpu_baseline_full(bits, fmt, terms=None, budget_s=3.0):
         acc, threads = oracle.exact_sum_binned(bits, fmt)
         times.append(time.time() - t0)
     times.sort()
-    want = tuple(oracle.finish(acc, fmt))
+    want = tuple(oracle.finish(acc, "f32" if fmt == "bf16" else fmt))
     closed = terms is None or oracle.exact_sum_binned(terms, fmt)[0].total == acc.total
     sign_bit = {"f64": np.uint64(1 << 63), "f32": np.uint32(1 << 31),
                 "bf16": np.uint16(1 << 15)}[fmt]
@@ -112,13 +115,17 @@ def cpu_baseline_sample(pieces, threads=16):
     return results, sum(len(b) for b, _ in pieces), secs, threads
 
 
-def ulps_between(a, b):
-    """Distance in units in the last place of b between doubles a and b."""
+def ulps_between(a, b, fmt="f64"):
+    """Distance between a and b in units in the last place of b, where b is a
+    binary64 (fmt "f64") or binary32 (fmt "f32") value."""
     if a == b:
         return 0.0
     if b == 0 or not math.isfinite(a) or not math.isfinite(b):
         return float("inf")
-    return abs(a - b) / math.ulp(b)
+    if fmt == "f64":
+        return abs(a - b) / math.ulp(b)
+    e = max(math.frexp(b)[1] - 1, -126)          # binary32 exponent of b
+    return abs(a - b) / math.ldexp(1.0, e - 23)
 
 
 def main():
@@ -127,6 +134,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16"],
+                    help="input format of the single-sum workload (2 GiB each: "
+                         "2^28 binary64, 2^29 binary32, 2^30 bfloat16)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-torch-sum", action="store_true")
@@ -160,15 +170,35 @@ def main():
     import paper_1605_05436_amd as xs
     import workloads
 
-    n = 1 << args.log2n
-    log("generating config: n=2^%d binary64 cancelling pairs + perturbations"
-        % args.log2n)
+    fmt = args.dtype
+    code = {"f64": xs.F64, "f32": xs.F32, "bf16": xs.BF16}[fmt]
+    esize = {"f64": 8, "f32": 4, "bf16": 2}[fmt]
+    n = (1 << args.log2n) * 8 // esize      # the same bytes in every format
     t0 = time.time()
-    bits, terms = workloads.config2(log2n=args.log2n, seed=args.seed)
+    terms = None
+    if fmt == "f64":
+        log("generating config: n=2^%d binary64 cancelling pairs + perturbations"
+            % args.log2n)
+        bits, terms = workloads.config2(log2n=args.log2n, seed=args.seed)
+        workload = ("single exact sum, n=2^28 binary64, cancelling pairs + 1% "
+                    "perturbations, seeded shuffle")
+    elif fmt == "f32":
+        log("generating %d binary32 cancelling pairs + perturbations" % n)
+        bits = workloads.serving_payload(n, "f32", seed=args.seed)
+        workload = ("single exact sum, n=2^29 binary32, cancelling pairs + 1% "
+                    "perturbations, seeded shuffle")
+    else:
+        log("generating %d bfloat16 values, mixed signs, exponents in [-50, 50]" % n)
+        piece = min(n, 1 << 26)     # generated in pieces to bound host memory
+        bits = np.concatenate([workloads.family("mixed", piece, 100,
+                                                seed=args.seed * 4096 + i, fmt="bf16")
+                               for i in range(n // piece)])
+        workload = "single exact sum, n=2^30 bfloat16, mixed signs, exponents in [-50, 50]"
     log("generated in %.1f s" % (time.time() - t0))
 
     dev = torch.device("cuda:0")
-    x = torch.from_numpy(bits.view(np.int64)).to(dev)
+    signed = {8: np.int64, 4: np.int32, 2: np.int16}[esize]
+    x = torch.from_numpy(bits.view(signed)).to(dev)
     out = torch.zeros(1, dtype=torch.int64, device=dev)
     flags = torch.zeros(1, dtype=torch.int32, device=dev)
     scratch = xs.new_states(1)
@@ -177,7 +207,7 @@ def main():
     torch.cuda.synchronize()
 
     def step():
-        xs.xsum_exact_sum_async(x.data_ptr(), n, xs.F64, xs.F64, out.data_ptr(),
+        xs.xsum_exact_sum_async(x.data_ptr(), n, code, xs.SAME, out.data_ptr(),
                                 flags.data_ptr(), scratch.data_ptr(), sh)
 
     for _ in range(args.warmup):
@@ -193,23 +223,32 @@ def main():
     ms_total = ev0.elapsed_time(ev1)
     ms_per_step = ms_total / args.steps
     gelem_s = n * args.steps / (ms_total * 1e-3) / 1e9
-    result_bits = int(out.cpu().numpy().view(np.uint64)[0])
+    out_fmt = "f64" if fmt == "f64" else "f32"
+    result_bits = int(out.cpu().numpy().view(np.uint64)[0]) & \
+        ((1 << (8 * (8 if out_fmt == "f64" else 4))) - 1)
     result_flags = int(flags.cpu()[0])
     log("exact sum: %.3f ms/step, %.1f Gelem/s" % (ms_per_step, gelem_s))
 
     # parity of the timed result against the oracle (closed form: the sum of
     # the replaced pairs equals the sum of everything)
     (want_bits, want_flags), closed, threads, cpu_s, cpu_runs, log10_cond = \
-        cpu_baseline_full(bits, "f64", terms)
+        cpu_baseline_full(bits, fmt, terms)
     bit_exact = (result_bits, result_flags) == (want_bits, want_flags) and closed
-    exact_val = struct.unpack("<d", struct.pack("<Q", want_bits))[0]
+    if out_fmt == "f64":
+        exact_val = struct.unpack("<d", struct.pack("<Q", want_bits))[0]
+    else:
+        exact_val = float(struct.unpack("<f", struct.pack("<I", want_bits))[0])
     log("oracle: %.3f s per run (median of %d) on %d threads, bit_exact=%s"
         % (cpu_s, cpu_runs, threads, bit_exact))
 
-    alg_bytes = n * 8
+    alg_bytes = n * esize
     achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
+    metric = ("exact FP64 sum Gelem/s + % HBM roofline vs torch.sum on same GPU (bit-exact)"
+              if fmt == "f64" else
+              "exact %s sum Gelem/s + %% roofline vs torch.sum on same GPU (bit-exact)"
+              % {"f32": "binary32", "bf16": "bfloat16"}[fmt])
     rec = {
-        "metric": "exact FP64 sum Gelem/s + % HBM roofline vs torch.sum on same GPU (bit-exact)",
+        "metric": metric,
         "value": round(gelem_s, 2),
         "unit": "Gelem/s",
         "n_gpus": 1,
@@ -221,25 +260,26 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "single exact sum, n=2^28 binary64, cancelling "
-                               "pairs + 1% perturbations, seeded shuffle",
-                   "n": n, "input_dtype": "f64", "out_dtype": "f64",
+        "config": {"workload": workload,
+                   "n": n, "input_dtype": fmt, "out_dtype": out_fmt,
                    "seed": args.seed},
         "bit_exact": bit_exact,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(n)},
+                     "traffic": measured_traffic(n, profile=TRAFFIC_PROFILES[fmt])},
     }
 
     if not args.no_torch_sum:
-        xf = x.view(torch.float64)
+        xf = x.view({"f64": torch.float64, "f32": torch.float32,
+                     "bf16": torch.bfloat16}[fmt])
+        sum_dtype = torch.float32 if fmt == "bf16" else None
         for _ in range(3):
-            s = torch.sum(xf)
+            s = torch.sum(xf, dtype=sum_dtype)
         torch.cuda.synchronize()
         ev0.record(stream)
         for _ in range(args.steps):
-            s = torch.sum(xf)
+            s = torch.sum(xf, dtype=sum_dtype)
         ev1.record(stream)
         torch.cuda.synchronize()
         tms = ev0.elapsed_time(ev1) / args.steps
@@ -247,7 +287,7 @@ def main():
         rec["torch_sum"] = {"ms_per_step": round(tms, 4),
                             "gelem_s": round(n / (tms * 1e-3) / 1e9, 2),
                             "value": tval, "exact_rounded": exact_val,
-                            "error_ulps": ulps_between(tval, exact_val),
+                            "error_ulps": ulps_between(tval, exact_val, out_fmt),
                             "log10_condition_number": log10_cond,
                             "rel_error": (abs(tval - exact_val) / abs(exact_val)
                                           if exact_val else None)}
@@ -256,16 +296,16 @@ def main():
         y = torch.empty_like(x)
         y.copy_(x)
         torch.cuda.synchronize()
-        rec["copy_calibration_bytes"] = {"read": n * 8, "write": n * 8}
+        rec["copy_calibration_bytes"] = {"read": n * esize, "write": n * esize}
         del y
 
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = {"value": round(n / cpu_s / 1e9, 4),
                                "unit": "Gelem/s", "cores": threads,
                                "kind": "oracle",
-                               "sample": "the full n=2^28 input, median of %d runs "
+                               "sample": "the full n=%d input, median of %d runs "
                                          "(exponent-binned 128-bit C accumulation + "
-                                         "big-int fold + RNE rounding)" % cpu_runs}
+                                         "big-int fold + RNE rounding)" % (n, cpu_runs)}
     print(json.dumps(rec), flush=True)
 
 

@@ -248,7 +248,8 @@ typedef struct xsum_segment {
  *                 16384 / 32768 for binary64 / binary32 / bfloat16: 64 KiB of
  *                 input; at most 2^20 / 2^22 / 2^23)
  *   wave_max[d]   longer segments with at most this many elements are summed
- *                 whole by one wave (default: 4 MiB of input)
+ *                 whole by one wave (default: 4 MiB of input; values above
+ *                 2^36 act as 2^36)
  *   chunk_vectors longer segments still are cut into chunks of this many
  *                 16-byte vectors, summed by separate waves whose states are
  *                 merged (default 2^18 = 4 MiB, range [64, 2^26])

@@ -18,15 +18,21 @@
 //             k+1.  A digit thus absorbs about 2^10 chunks before it must be
 //             carried, so every lane carry-normalises its own column every
 //             few hundred elements (cheap, LDS-local, sequential per lane).
-//   binary32: the column is indexed by byte position instead: p = max(E,1) +
-//             924, bin b = p >> 3, r = p & 7, T = +-m 2^r fits in 32 signed
-//             bits and is added as one chunk into bin b (weight 2^(8b)); a
-//             64-bit bin absorbs 2^31 chunks, so no normalisation is needed.
-//   bfloat16: the upper half of a binary32 (exact widening), as binary32.
+//   binary32: the column is indexed by byte position and sign instead:
+//             p = max(E,1) + 924, bin b = p >> 3, r = p & 7; the magnitude
+//             m 2^r < 2^31 is added as one chunk to entry 2b (positive inputs)
+//             or 2b + 1 (negative inputs) of the bin, which weighs 2^(8b).
+//             Unsigned 64-bit entries absorb 2^33 chunks, so no normalisation
+//             is needed, and keeping the sign in the entry index spares the
+//             negation and the sign extension of every chunk.
+//   bfloat16: as binary32 with the 8-bit significand: p = max(E,1) + 940,
+//             magnitude m 2^r < 2^15.  Two elements (one 32-bit word) are
+//             decoded at once with packed 16-bit integer operations.
 // Infinities and NaNs (all-ones exponent) take the finite path like any other
-// bit pattern; every lane tracks the largest exponent field it saw, and after
-// each tile the rare lanes that saw an all-ones exponent record the special
-// value and add its negation, which cancels its contribution exactly.
+// bit pattern; every lane tracks the largest exponent field (binary64) or
+// magnitude (the binned formats) it saw, and after each tile the rare lanes
+// that saw an all-ones exponent record the special value and add it again
+// with the opposite sign, which cancels its contribution exactly.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,23 +54,27 @@ template <int FMT> struct Geo;
 template <> struct Geo<XSUM_F64> {
     static constexpr int kN = 66;          // column entries per lane
     static constexpr int kPerVec = 2, kBytes = 8;
-    static constexpr uint32_t kEspec = 0x7ffu;
+    static constexpr uint32_t kSpecFrom = 0x7ffu;   // tracked: exponent field
     static constexpr bool kBinned = false;
 };
-// binary32 / bfloat16: 33 byte-position bins, p >> 3 in [115, 147].
+// binary32 / bfloat16: 33 byte-position bins (p >> 3 in [115, 147] and
+// [117, 149]), two entries each: 2b for positive and 2b + 1 for negative
+// magnitudes.
 template <> struct Geo<XSUM_F32> {
-    static constexpr int kN = 33;
+    static constexpr int kN = 66;
     static constexpr int kPerVec = 4, kBytes = 4;
-    static constexpr uint32_t kEspec = 0xffu;
+    static constexpr uint32_t kSpecFrom = 0x7f800000u;   // tracked: magnitude bits
     static constexpr bool kBinned = true;
-    static constexpr int kBin0 = 115;      // bin of column entry 0
+    static constexpr int kBins = 33;
+    static constexpr int kBin0 = 115;      // byte position of bin 0
 };
 template <> struct Geo<XSUM_BF16> {
-    static constexpr int kN = 33;
+    static constexpr int kN = 66;
     static constexpr int kPerVec = 8, kBytes = 2;
-    static constexpr uint32_t kEspec = 0xffu;
+    static constexpr uint32_t kSpecFrom = 0x7f80u;       // tracked: magnitude bits
     static constexpr bool kBinned = true;
-    static constexpr int kBin0 = 115;
+    static constexpr int kBins = 33;
+    static constexpr int kBin0 = 117;
 };
 
 __device__ __forceinline__ void lds_add(uint64_t *p, uint64_t v)
@@ -109,18 +119,44 @@ __device__ __forceinline__ void add_f64(uint32_t lo, uint32_t hi,
     lds_add(d + 64, (uint64_t)c1);
 }
 
-// One binary32 element (a bfloat16 arrives widened by a 16-bit shift).
+// One binary32 element into the lane's column; amax keeps the largest
+// magnitude bits seen (an all-ones exponent field makes it 0x7f800000 or more).
 __device__ __forceinline__ void add_f32(uint32_t b, uint64_t *col,
-                                        uint32_t &emax)
+                                        uint32_t &amax)
 {
-    const uint32_t e = (b >> 23) & 0xffu;
-    emax = max(emax, e);
-    const uint32_t q = max(e, 1u) + 4u;   // p - 8*115, p = max(E,1) + 924
-    const int32_t m = (int32_t)((b & 0x7fffffu) | (min(e, 1u) << 23));
-    const int32_t sm = (int32_t)b >> 31;
-    const int32_t v = (m ^ sm) - sm;
-    const int32_t t = (int32_t)((uint32_t)v << (q & 7u));  // |t| < 2^31
-    lds_add(col + (q >> 3) * 64, (uint64_t)(int64_t)t);
+    const uint32_t a = b & 0x7fffffffu;
+    amax = max(amax, a);
+    // bits 23 and up: q = max(E,1) + 4 = p - 8*115, p = max(E,1) + 924
+    const uint32_t u = max(a, 0x00800000u) + (4u << 23);
+    // significand with its hidden bit (min(a, 2^23) is 2^23 exactly when E > 0)
+    const uint32_t m = (a & 0x7fffffu) | min(a, 0x00800000u);
+    const uint32_t t = m << ((u >> 23) & 7u);   // < 2^31
+    // entry 2 (q >> 3) + sign: the bin index and the sign bit side by side
+    const uint32_t idx = __builtin_amdgcn_alignbit(u >> 26, b, 31);
+    lds_add(col + idx * 64, (uint64_t)t);
+}
+
+// Two bfloat16 elements (the halves of w) into the lane's column; amax keeps
+// the largest magnitude bits seen in each half.
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void add_bf16_pair(uint32_t w, uint64_t *col,
+                                              u16x2 &amax)
+{
+    const u16x2 h = __builtin_bit_cast(u16x2, w);
+    const u16x2 a = h & (u16x2)0x7fffu;
+    amax = __builtin_elementwise_max(amax, a);
+    // bits 7 to 15: q = max(E,1) + 4 = p - 8*117, p = max(E,1) + 940
+    const u16x2 u = __builtin_elementwise_max(a, (u16x2)0x80u) + (u16x2)0x200u;
+    const u16x2 m = (a & (u16x2)0x7fu) | __builtin_elementwise_min(a, (u16x2)0x80u);
+    const u16x2 t = m << ((u >> (u16x2)7) & (u16x2)7);   // < 2^15
+    // byte offset of entry 2 (q >> 3) + sign (entries are 512 bytes apart):
+    // q >> 3 sits in bits 10 to 15 of u, the sign goes to bit 9
+    const uint32_t off = (__builtin_bit_cast(uint32_t, u) & 0xfc00fc00u) |
+                         ((w >> 6) & 0x02000200u);
+    char *base = (char *)col;
+    lds_add((uint64_t *)(base + (off & 0xffffu)), (uint64_t)t.x);
+    lds_add((uint64_t *)(base + (off >> 16)), (uint64_t)t.y);
 }
 
 template <int FMT>
@@ -136,14 +172,12 @@ __device__ __forceinline__ void add_vec(const vec4u &q, uint64_t *col,
         add_f32(q.z, col, emax);
         add_f32(q.w, col, emax);
     } else {
-        add_f32(q.x << 16, col, emax);
-        add_f32(q.x & 0xffff0000u, col, emax);
-        add_f32(q.y << 16, col, emax);
-        add_f32(q.y & 0xffff0000u, col, emax);
-        add_f32(q.z << 16, col, emax);
-        add_f32(q.z & 0xffff0000u, col, emax);
-        add_f32(q.w << 16, col, emax);
-        add_f32(q.w & 0xffff0000u, col, emax);
+        u16x2 em = __builtin_bit_cast(u16x2, emax);
+        add_bf16_pair(q.x, col, em);
+        add_bf16_pair(q.y, col, em);
+        add_bf16_pair(q.z, col, em);
+        add_bf16_pair(q.w, col, em);
+        emax = __builtin_bit_cast(uint32_t, em);
     }
 }
 
@@ -169,6 +203,26 @@ __device__ __forceinline__ void fix_f32(uint32_t b, uint64_t *col,
     }
 }
 
+// The same for the two bfloat16 halves of w: the special halves are added
+// again with the opposite sign, the others are replaced by +0 (which adds 0).
+__device__ __forceinline__ void fix_bf16_pair(uint32_t w, uint64_t *col,
+                                              uint32_t &spec)
+{
+    uint32_t neg = 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const uint32_t hk = (w >> (16 * k)) & 0xffffu;
+        if (((hk >> 7) & 0xffu) == 0xffu) {
+            spec |= special_bits((hk & 0x7fu) != 0, (hk >> 15) != 0);
+            neg |= (hk ^ 0x8000u) << (16 * k);
+        }
+    }
+    if (neg) {
+        u16x2 dummy = (u16x2)0;
+        add_bf16_pair(neg, col, dummy);
+    }
+}
+
 template <int FMT>
 __device__ __forceinline__ void fix_vec(const vec4u &q, uint64_t *col,
                                         uint32_t &spec)
@@ -182,14 +236,10 @@ __device__ __forceinline__ void fix_vec(const vec4u &q, uint64_t *col,
         fix_f32(q.z, col, spec);
         fix_f32(q.w, col, spec);
     } else {
-        fix_f32(q.x << 16, col, spec);
-        fix_f32(q.x & 0xffff0000u, col, spec);
-        fix_f32(q.y << 16, col, spec);
-        fix_f32(q.y & 0xffff0000u, col, spec);
-        fix_f32(q.z << 16, col, spec);
-        fix_f32(q.z & 0xffff0000u, col, spec);
-        fix_f32(q.w << 16, col, spec);
-        fix_f32(q.w & 0xffff0000u, col, spec);
+        fix_bf16_pair(q.x, col, spec);
+        fix_bf16_pair(q.y, col, spec);
+        fix_bf16_pair(q.z, col, spec);
+        fix_bf16_pair(q.w, col, spec);
     }
 }
 
@@ -198,11 +248,13 @@ template <int FMT, int U>
 __device__ __forceinline__ void add_tile(const vec4u (&q)[U], uint64_t *col,
                                          uint32_t &spec)
 {
-    uint32_t emax = 0;
+    uint32_t emax = 0;      // largest exponent field (binary64) or magnitude
 #pragma unroll
     for (int j = 0; j < U; ++j)
         add_vec<FMT>(q[j], col, emax);
-    if (__builtin_expect(emax == Geo<FMT>::kEspec, 0)) {
+    if constexpr (FMT == XSUM_BF16)     // two 16-bit fields
+        emax = max(emax & 0xffffu, emax >> 16);
+    if (__builtin_expect(emax >= Geo<FMT>::kSpecFrom, 0)) {
 #pragma unroll
         for (int j = 0; j < U; ++j)
             fix_vec<FMT>(q[j], col, spec);
@@ -219,14 +271,15 @@ __device__ __forceinline__ void add_scalar(const uint8_t *p, uint64_t *col,
         const uint32_t *w = (const uint32_t *)p;
         add_f64(w[0], w[1], col, emax);
         fix_f64(w[0], w[1], col, spec);
-    } else {
-        uint32_t b;
-        if constexpr (FMT == XSUM_F32)
-            b = *(const uint32_t *)p;
-        else
-            b = (uint32_t)(*(const uint16_t *)p) << 16;
+    } else if constexpr (FMT == XSUM_F32) {
+        const uint32_t b = *(const uint32_t *)p;
         add_f32(b, col, emax);
         fix_f32(b, col, spec);
+    } else {
+        const uint32_t w = *(const uint16_t *)p;    // upper half +0, adds 0
+        u16x2 em = (u16x2)0;
+        add_bf16_pair(w, col, em);
+        fix_bf16_pair(w, col, spec);
     }
 }
 
@@ -252,24 +305,53 @@ __device__ __forceinline__ void normalise_column(uint64_t *col)
         lds_store(col + d * 64, (uint64_t)v[d]);
 }
 
-// Block merge of one wave's columns.  Lane l takes column entry l: it sums
-// that entry over the wave's 64 lanes, reading lane (c + l) mod 64 so the 64
-// lanes hit distinct banks.  Each entry splits as lo + hi 2^32 (lo in
-// [0, 2^32)) before summing so nothing can overflow; the sums go to the
-// block's digit vector blk with LDS atomics.  Binary32 bins (weight 2^(8b))
-// are first moved to their radix-2^32 digit.  Binary64 entries 64 and 65 only
-// receive chunks of inputs of magnitude 2^994 and above (and their carries),
-// so instead of a second pass each lane adds its own two top entries, and only
-// when one of them is non-zero anywhere in the wave.
+// Add lo + hi 2^32 (lo in [0, 2^38), |hi| < 2^37) times the weight of column
+// row d to the block's digit vector blk with LDS atomics.  A binary64 row is
+// digit d itself; a binned row 2b + s is bin b (weight 2^(8(kBin0 + b))),
+// negated for s = 1, moved onto its radix-2^32 digit by a byte shift.
+template <int FMT>
+__device__ __forceinline__ void add_row(int64_t *blk, int d, uint64_t lo, int64_t hi)
+{
+    using G = Geo<FMT>;
+    int digit, shift;
+    bool neg = false;
+    if constexpr (G::kBinned) {
+        const int bin = G::kBin0 + (d >> 1);
+        digit = bin >> 2;
+        shift = 8 * (bin & 3);
+        neg = (d & 1) != 0;
+    } else {
+        digit = d;
+        shift = 0;
+    }
+    // each shifted term stays below 2^62
+    const uint64_t ls = lo << shift;
+    const int64_t hs = (int64_t)((uint64_t)hi << shift);
+    int64_t parts[3] = {(int64_t)(ls & kLow32),
+                        (int64_t)(ls >> 32) + (int64_t)((uint64_t)hs & kLow32), hs >> 32};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (parts[i])
+            __hip_atomic_fetch_add(&blk[digit + i], neg ? -parts[i] : parts[i],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Block merge of one wave's columns.  Lane l takes column row l: it sums that
+// row over the wave's 64 lanes, reading lane (c + l) mod 64 so the 64 lanes
+// hit distinct banks.  Each entry splits as lo + hi 2^32 (lo in [0, 2^32))
+// before summing so nothing can overflow; the sums go to the block's digit
+// vector.  Rows 64 and 65 only receive chunks of inputs of magnitude 2^994
+// and above in binary64 (and their carries), and of 2^125 and above in the
+// binned formats, so instead of a second pass each lane adds its own two top
+// entries, and only when one of them is non-zero anywhere in the wave.
 template <int FMT>
 __device__ __forceinline__ void merge_wave_columns(uint64_t (*cols)[64],
                                                    int64_t *blk, int lane)
 {
     using G = Geo<FMT>;
-    static_assert(G::kN <= 66, "at most two entries above the lanes");
-    if (lane < G::kN) {
-        const int d = lane;
-        const uint64_t *row = cols[d];
+    static_assert(G::kN == 66, "two rows above the lanes");
+    {
+        const uint64_t *row = cols[lane];
         uint64_t lo = 0;
         int64_t hi = 0;
 #pragma unroll 16
@@ -278,48 +360,20 @@ __device__ __forceinline__ void merge_wave_columns(uint64_t (*cols)[64],
             lo += val & kLow32;
             hi += (int64_t)val >> 32;
         }
-        int digit, shift;
-        if constexpr (G::kBinned) {
-            const int bin = G::kBin0 + d;
-            digit = bin >> 2;
-            shift = 8 * (bin & 3);
-        } else {
-            digit = d;
-            shift = 0;
-        }
-        // lo < 2^38 and |hi| < 2^37, so each shifted term stays below 2^62
-        const uint64_t ls = lo << shift;
-        const int64_t hs = (int64_t)((uint64_t)hi << shift);
-        const int64_t parts[3] = {(int64_t)(ls & kLow32),
-                                  (int64_t)(ls >> 32) + (int64_t)((uint64_t)hs & kLow32),
-                                  hs >> 32};
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-            if (parts[i])
-                __hip_atomic_fetch_add(&blk[digit + i], parts[i],
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        add_row<FMT>(blk, lane, lo, hi);
     }
-    if constexpr (G::kN > 64) {
-        uint64_t top[G::kN - 64];
-        bool any = false;
+    uint64_t top[2];
+    bool any = false;
 #pragma unroll
-        for (int r = 0; r < G::kN - 64; ++r) {
-            top[r] = cols[64 + r][lane];
-            any |= top[r] != 0;
-        }
-        if (__ballot(any)) {
+    for (int r = 0; r < 2; ++r) {
+        top[r] = cols[64 + r][lane];
+        any |= top[r] != 0;
+    }
+    if (__ballot(any)) {
 #pragma unroll
-            for (int r = 0; r < G::kN - 64; ++r) {
-                const int64_t lo = (int64_t)(top[r] & kLow32);
-                const int64_t hi = (int64_t)top[r] >> 32;
-                if (lo)
-                    __hip_atomic_fetch_add(&blk[64 + r], lo, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (hi)
-                    __hip_atomic_fetch_add(&blk[65 + r], hi, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-        }
+        for (int r = 0; r < 2; ++r)
+            if (top[r])
+                add_row<FMT>(blk, 64 + r, top[r] & kLow32, (int64_t)top[r] >> 32);
     }
 }
 

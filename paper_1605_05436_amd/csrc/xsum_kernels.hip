@@ -38,6 +38,10 @@ namespace xsum {
 // fewer than (kNormTiles + 2)*U*2 + 2 < 2047 elements, each adding below
 // 2^32 + 2^52 to a digit that started below 2^32: every entry stays below
 // 2^63 and its high word below 2^31 in magnitude, as the block merge assumes.
+// Binned (binary32, bfloat16) entries only grow.  The launcher gives every
+// block at most 2^24 tiles of U * kPerVec elements per lane (64 binary32, each
+// chunk below 2^31; 192 bfloat16, each below 2^15), so an entry stays below
+// 2^61 and its high word below 2^31, as the block merge assumes.
 template <int FMT, int WAVES, int U, bool WAVE_CONTIG>
 __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
     const uint8_t *__restrict__ x, uint32_t head, uint64_t nvec,
@@ -49,6 +53,8 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
     constexpr int kNormTiles = 512 / U;
     static_assert(FMT != XSUM_F64 || (kNormTiles + 2) * U * 2 + 2 < 2047,
                   "binary64 column headroom");
+    static_assert(FMT == XSUM_F64 || (FMT == XSUM_F32 ? U * 4 <= 64 : U * 8 <= 192),
+                  "binned column headroom");
     __shared__ uint64_t cols[WAVES][G::kN][64];
     __shared__ int64_t blk[kDigits];
     __shared__ uint32_t blk_spec;
@@ -216,22 +222,22 @@ int element_size(int dtype)
 }
 
 // Launch shapes (measured on MI355X with the timing harness, config-2-like
-// data): a binary64 column is 66 x 64 x 8 B = 33 KiB per wave, so two 2-wave
-// blocks fill a CU's 160 KiB of LDS; the 33-bin binary32 columns take 17 KiB
-// per wave.  Each wave keeps U 16-byte loads per lane in flight while it adds
-// the previous U; wave-contiguous tiles give each wave its own 64*U-vector
-// stream.
+// data): a column is 66 x 64 x 8 B = 33 KiB per wave in every format, so four
+// waves fill a CU's 160 KiB of LDS.  Each wave keeps U 16-byte loads per lane
+// in flight while it adds the previous U; wave-contiguous tiles give each wave
+// its own 64*U-vector stream.  bfloat16, with the most work per byte, runs
+// best as four one-wave blocks with deeper tiles.
 template <int FMT> struct Shape_;
 template <> struct Shape_<XSUM_F64> {
     static constexpr int kWaves = 2, kUnroll = 16, kBlocksPerCu = 2;
     static constexpr bool kWaveContig = true;
 };
 template <> struct Shape_<XSUM_F32> {
-    static constexpr int kWaves = 2, kUnroll = 16, kBlocksPerCu = 4;
+    static constexpr int kWaves = 2, kUnroll = 16, kBlocksPerCu = 2;
     static constexpr bool kWaveContig = true;
 };
 template <> struct Shape_<XSUM_BF16> {
-    static constexpr int kWaves = 1, kUnroll = 8, kBlocksPerCu = 8;
+    static constexpr int kWaves = 1, kUnroll = 24, kBlocksPerCu = 4;
     static constexpr bool kWaveContig = true;
 };
 
@@ -276,6 +282,9 @@ static hipError_t launch_fmt(const void *x, uint64_t n, xsum_acc_t *acc,
         if (want < blocks)
             blocks = want > kMinBlocks ? want : kMinBlocks;
     }
+    constexpr uint64_t kMaxTilesPerBlock = uint64_t(1) << 24;
+    if (blocks < (tiles + kMaxTilesPerBlock - 1) / kMaxTilesPerBlock)
+        blocks = (tiles + kMaxTilesPerBlock - 1) / kMaxTilesPerBlock;
     if (blocks > tiles)
         blocks = tiles;
     if (blocks < 1)

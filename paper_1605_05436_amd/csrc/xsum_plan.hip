@@ -123,6 +123,11 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
         blocks_per_cu = (int)tuning->blocks_per_cu;
         if (lane_max[0] > (1u << 20) || lane_max[1] > (1u << 22) || lane_max[2] > (1u << 23))
             return api_fail(XSUM_ERANGE, "lane_max too large");
+        // one wave sums a segment of up to wave_max elements: at most 2^30
+        // per lane keeps every binned column entry below 2^62
+        for (int d = 0; d < 3; ++d)
+            if (wave_max[d] > (uint64_t(1) << 36))
+                wave_max[d] = uint64_t(1) << 36;
         if (chunk_vectors < 64 || chunk_vectors > (1u << 26))
             return api_fail(XSUM_ERANGE, "chunk_vectors out of range [64, 2^26]");
         if (blocks_per_cu < 0 || blocks_per_cu > 16)

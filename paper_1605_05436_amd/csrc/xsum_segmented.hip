@@ -40,8 +40,8 @@ template <> struct LaneOut<XSUM_F64> { static constexpr int kNatural = XSUM_F64;
 template <> struct LaneOut<XSUM_F32> { static constexpr int kNatural = XSUM_F32; };
 template <> struct LaneOut<XSUM_BF16> { static constexpr int kNatural = XSUM_F32; };
 
-// Per-wave LDS: a binary64-sized column set (binary32 tasks use the first
-// 33 entries) and a 68-digit merge vector.
+// Per-wave LDS: a 66-row column set (every format uses all of it) and a
+// 68-digit merge vector.
 struct WaveLds {
     uint64_t cols[Geo<XSUM_F64>::kN][64];
     int64_t merged[kDigits];
@@ -82,10 +82,12 @@ __device__ __forceinline__ uint32_t wave_or_u32(uint32_t v)
 }
 
 // Round the lane's own column and zero it.  binary64 columns are digits
-// 0..65; binary32 bins (weight 2^(8(b + 115))) are first moved to radix-2^32
-// digits 28..39, written back over the bins they came from (digit 28 + i
-// lands in entry i, never past a bin still to be read), each bin split into
-// 32-bit halves so no shift overflows; two top digits take any carry.
+// 0..65.  A binned column holds 33 bins of weight 2^(8(b + kBin0)), each as a
+// positive and a negative entry; each bin's signed value is moved to its
+// radix-2^32 digit (kBin0 / 4 onwards), written back over the entries it came
+// from (digit kBin0 / 4 + i lands in entry i, never past an entry still to be
+// read), split into 32-bit halves so no shift overflows; two top digits take
+// any carry.
 template <int FMT>
 __device__ __forceinline__ uint64_t finish_lane(uint64_t *col, uint32_t spec,
                                                 int out_fmt, uint32_t &flags)
@@ -94,14 +96,15 @@ __device__ __forceinline__ uint64_t finish_lane(uint64_t *col, uint32_t spec,
         return finish_lane_digits<Geo<XSUM_F64>::kN>(col, 0, spec, out_fmt, flags);
     } else {
         constexpr int kBin0 = Geo<FMT>::kBin0;
-        constexpr int kDigit0 = kBin0 >> 2;        // 28
+        constexpr int kDigit0 = kBin0 >> 2;
         int64_t cur = 0, nxt = 0;                  // digits g and g + 1
         int g_prev = kDigit0;
 #pragma unroll
-        for (int b = 0; b < Geo<FMT>::kN; ++b) {
+        for (int b = 0; b < Geo<FMT>::kBins; ++b) {
             const int g = (b + kBin0) >> 2;
             const int sh = 8 * ((b + kBin0) & 3);
-            const int64_t v = (int64_t)lds_load(col + b * 64);
+            const int64_t v = (int64_t)lds_load(col + (2 * b) * 64) -
+                              (int64_t)lds_load(col + (2 * b + 1) * 64);
             if (g != g_prev) {
                 lds_store(col + (g_prev - kDigit0) * 64, (uint64_t)cur);
                 cur = nxt;
@@ -113,15 +116,15 @@ __device__ __forceinline__ uint64_t finish_lane(uint64_t *col, uint32_t spec,
             cur += (int64_t)(lo & kLow32);
             nxt += (int64_t)(lo >> 32) + hi;
         }
-        // digits 36 and 37, then two empty digits for the carry
-        constexpr int kLast = (Geo<FMT>::kN - 1 + kBin0) >> 2;   // 36
+        // the last two digits, then two empty digits for the carry
+        constexpr int kLast = (Geo<FMT>::kBins - 1 + kBin0) >> 2;
         lds_store(col + (kLast - kDigit0) * 64, (uint64_t)cur);
         lds_store(col + (kLast + 1 - kDigit0) * 64, (uint64_t)nxt);
         lds_store(col + (kLast + 2 - kDigit0) * 64, 0);
         lds_store(col + (kLast + 3 - kDigit0) * 64, 0);
         const uint64_t bits = finish_lane_digits<kLast + 4 - kDigit0>(col, kDigit0, spec,
                                                                       out_fmt, flags);
-        // bins above the digits (entries 12..32) were left as they were
+        // entries above the digits were left as they were
 #pragma unroll
         for (int b = kLast + 4 - kDigit0; b < Geo<FMT>::kN; ++b)
             lds_store(col + b * 64, 0);
