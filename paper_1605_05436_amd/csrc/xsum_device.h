@@ -695,37 +695,27 @@ __device__ __forceinline__ void store_result(void *out, int out_fmt,
         *(uint16_t *)out = (uint16_t)bits;
 }
 
-__device__ __forceinline__ int64_t gload(const int64_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void gstore(int64_t *p, int64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Last-block work of an accumulation launch, run by one full wave.
+// Last-block work of an accumulation launch, run by one full wave.  GRID is
+// the single-sum kernel: its blocks publish with system-scope atomics, so
+// every state access here is system-scope too.  Otherwise (agent scope) the
+// caller orders the accesses with agent-scope fences.
+template <bool GRID>
 static __device__ __forceinline__ void finish_state(xsum_acc_t *acc, const Finish &fin, int lane)
 {
+    constexpr int kScope = GRID ? __HIP_MEMORY_SCOPE_SYSTEM : __HIP_MEMORY_SCOPE_AGENT;
     int64_t a = 0, b = 0;
     const bool live = lane <= 33;
-    uint32_t special;
-    if (fin.mode == kRound) {
+    if (fin.mode == kRound) {       // take the digits and leave zeros
         if (live) {
-            a = (int64_t)atomicExch((unsigned long long *)&acc->digit[2 * lane], 0ull);
-            b = (int64_t)atomicExch((unsigned long long *)&acc->digit[2 * lane + 1], 0ull);
+            a = __hip_atomic_exchange(&acc->digit[2 * lane], (int64_t)0, __ATOMIC_RELAXED, kScope);
+            b = __hip_atomic_exchange(&acc->digit[2 * lane + 1], (int64_t)0, __ATOMIC_RELAXED,
+                                      kScope);
         }
-        special = __hip_atomic_load(&acc->special, __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        if (live) {
-            a = gload(&acc->digit[2 * lane]);
-            b = gload(&acc->digit[2 * lane + 1]);
-        }
-        special = __hip_atomic_load(&acc->special, __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
+    } else if (live) {
+        a = __hip_atomic_load(&acc->digit[2 * lane], __ATOMIC_RELAXED, kScope);
+        b = __hip_atomic_load(&acc->digit[2 * lane + 1], __ATOMIC_RELAXED, kScope);
     }
+    const uint32_t special = __hip_atomic_load(&acc->special, __ATOMIC_RELAXED, kScope);
     normalise_wave(a, b, lane);
     if (fin.mode == kRound) {
         uint32_t flags;
@@ -737,19 +727,16 @@ static __device__ __forceinline__ void finish_state(xsum_acc_t *acc, const Finis
                 store_result(fin.out, fin.out_fmt, bits);
             if (fin.flags)
                 *fin.flags = flags;
-            __hip_atomic_store(&acc->special, 0u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&acc->ticket, 0u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&acc->special, 0u, __ATOMIC_RELAXED, kScope);
+            __hip_atomic_store(&acc->ticket, 0u, __ATOMIC_RELAXED, kScope);
         }
     } else {
         if (live) {
-            gstore(&acc->digit[2 * lane], a);
-            gstore(&acc->digit[2 * lane + 1], b);
+            __hip_atomic_store(&acc->digit[2 * lane], a, __ATOMIC_RELAXED, kScope);
+            __hip_atomic_store(&acc->digit[2 * lane + 1], b, __ATOMIC_RELAXED, kScope);
         }
         if (lane == 0)
-            __hip_atomic_store(&acc->ticket, 0u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&acc->ticket, 0u, __ATOMIC_RELAXED, kScope);
     }
 }
 

@@ -145,25 +145,36 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
     __syncthreads();
 
     // Grid merge: add the block's non-zero digits into the global state.
+    // Every access to the state is a system-scope atomic read-modify-write,
+    // performed at the memory side past every XCD's L2, so publishing needs
+    // no L2 write-back: each block only waits until its own atomics have
+    // completed before it takes its ticket (an agent-scope release fence
+    // would write back the XCD's whole L2 once per block while the other
+    // blocks still stream, which costs several percent of a large sum).
     for (int d = tid; d < kDigits; d += kThreads) {
         const int64_t dv = blk[d];
         if (dv)
-            atomicAdd((unsigned long long *)&acc->digit[d], (unsigned long long)dv);
+            __hip_atomic_fetch_add(&acc->digit[d], dv, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (tid == 0 && blk_spec)
-        atomicOr(&acc->special, blk_spec);
-    __threadfence();
+        __hip_atomic_fetch_or(&acc->special, blk_spec, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_SYSTEM);
+    // the fence keeps the atomics above this point; the wait (every counter
+    // zero) returns once they have completed at the memory side
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) {
-        const unsigned t = atomicAdd(&acc->ticket, 1u);
+        const unsigned t = __hip_atomic_fetch_add(&acc->ticket, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_SYSTEM);
         is_last = (t == gridDim.x - 1);
     }
     __syncthreads();
     if (!is_last)
         return;
-    __threadfence();
     if (wave == 0)
-        finish_state(acc, fin, lane);
+        finish_state<true>(acc, fin, lane);
 }
 
 // --------------------------------------------------- small state kernels --

@@ -424,7 +424,7 @@ __device__ __forceinline__ void run_chunk(const uint8_t *base, const SegDesc *se
         __threadfence();
         const int of = out_mode == XSUM_SAME ? LaneOut<FMT>::kNatural : out_mode;
         Finish fin{kRound, of, out + s, flags ? flags + s : nullptr, 1};
-        finish_state(st, fin, lane);
+        finish_state<false>(st, fin, lane);
     }
 }
 
@@ -639,7 +639,7 @@ __global__ __launch_bounds__(64) void batch_finalize_kernel(
     const int lane = threadIdx.x;
     xsum_acc_t *st = &states[slots[i]];
     Finish fin{kRound, (int)fmts[i], out + i, flags ? flags + i : nullptr, 1};
-    finish_state(st, fin, lane);
+    finish_state<false>(st, fin, lane);
 }
 
 hipError_t launch_batch_add(const BatchItem *items, uint32_t nitems,

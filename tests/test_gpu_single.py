@@ -105,6 +105,39 @@ def test_async_reuses_scratch_and_sizes_shrink():
         assert state == bytes(576)
 
 
+@pytest.mark.parametrize("fmt,kind", [("f64", "mixed"), ("f64", "zero_sum"),
+                                      ("f32", "mixed"), ("bf16", "positive")])
+def test_large_inputs_many_blocks(fmt, kind):
+    """Every block publishes its partial digits to the scratch state with
+    system-scope atomics and the last one rounds: the bits do not depend on
+    the grid, and the state is left zero."""
+    bits = workloads.family(kind, 2_000_003, 200 if fmt != "f64" else 2000, seed=31, fmt=fmt)
+    ref = want(bits, fmt)
+    t = to_device(bits)
+    for blocks in (0, 3, 977, 4000):
+        v, f, state = gpu_sum_async(t, len(bits), fmt, blocks=blocks)
+        assert (v, f) == ref, blocks
+        assert state == bytes(576), blocks
+
+
+def test_specials_published_by_distant_blocks():
+    """Special values seen by blocks far apart all reach the result; one
+    scratch state serves calls of shrinking sizes, the empty sum included."""
+    import paper_1605_05436_amd as xs
+    st = xs.new_states(1)
+    rng = np.random.default_rng(3)
+    for n in (1_500_007, 300_001, 4_097, 17, 0):
+        bits = workloads.family("mixed", n, 2000, seed=n)
+        if n > 100:
+            pos = rng.choice(n, size=2, replace=False)
+            bits[pos[0]] = np.uint64(0x7ff0000000000000)           # +inf
+            if n % 2:
+                bits[pos[1]] = np.uint64(0xfff0000000000000)       # -inf -> NaN
+        v, f, state = gpu_sum_async(to_device(bits), n, "f64", scratch=st)
+        assert (v, f) == want(bits, "f64"), n
+        assert state == bytes(576)
+
+
 def test_carry_stress_many_max_values():
     dmax = workloads.DBL_MAX_BITS
     bits = np.full(1_000_000, dmax, dtype=np.uint64)
@@ -161,3 +194,4 @@ def test_graph_capture_replays_match_eager():
         assert st.cpu().numpy().tobytes() == bytes(576)
         # eager work on another stream and tensor between the replays
         assert xs.exact_sum(xo, xs.F64) == want(other, "f64")
+
