@@ -695,14 +695,14 @@ __device__ __forceinline__ void store_result(void *out, int out_fmt,
         *(uint16_t *)out = (uint16_t)bits;
 }
 
-// Last-block work of an accumulation launch, run by one full wave.  GRID is
-// the single-sum kernel: its blocks publish with system-scope atomics, so
-// every state access here is system-scope too.  Otherwise (agent scope) the
-// caller orders the accesses with agent-scope fences.
-template <bool GRID>
+// Last-block work of an accumulation launch, run by one full wave.  SYS: the
+// state was filled with system-scope atomics by other waves of this launch,
+// so every access here is system-scope too.  Otherwise the state comes from
+// earlier launches and agent scope suffices.
+template <bool SYS>
 static __device__ __forceinline__ void finish_state(xsum_acc_t *acc, const Finish &fin, int lane)
 {
-    constexpr int kScope = GRID ? __HIP_MEMORY_SCOPE_SYSTEM : __HIP_MEMORY_SCOPE_AGENT;
+    constexpr int kScope = SYS ? __HIP_MEMORY_SCOPE_SYSTEM : __HIP_MEMORY_SCOPE_AGENT;
     int64_t a = 0, b = 0;
     const bool live = lane <= 33;
     if (fin.mode == kRound) {       // take the digits and leave zeros

@@ -284,10 +284,10 @@ static hipError_t launch_fmt(const void *x, uint64_t n, xsum_acc_t *acc,
     if (shape.blocks > 0) {
         blocks = (uint64_t)shape.blocks;
     } else {
-        // Every block pays a fixed merge, a device-scope fence and a ticket,
-        // so a small input gets about one block per 64 KiB (at least 32
-        // blocks to keep the loads spread), a large one the persistent grid.
-        constexpr uint64_t kVectorsPerBlock = 4096, kMinBlocks = 32;
+        // Every block pays a fixed merge, its grid atomics and a ticket, so
+        // a small input gets about one block per 16 KiB (at least 32 blocks
+        // to keep the loads spread), a large one the persistent grid.
+        constexpr uint64_t kVectorsPerBlock = 1024, kMinBlocks = 32;
         blocks = (uint64_t)persistent_blocks(FMT, cu_count);
         const uint64_t want = (nvec + kVectorsPerBlock - 1) / kVectorsPerBlock;
         if (want < blocks)

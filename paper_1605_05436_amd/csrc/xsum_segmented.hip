@@ -407,24 +407,31 @@ __device__ __forceinline__ void run_chunk(const uint8_t *base, const SegDesc *se
     merge_and_clear<FMT>(w, col, lane);
     spec = wave_or_u32(spec);
 
+    // The chunk's digits go to the segment's state with system-scope atomics
+    // (performed past the L2s, so no write-back fence is needed); the wave
+    // waits until they have completed before it takes its ticket, and the
+    // wave with the last ticket reads the state with system-scope atomics.
     xsum_acc_t *st = &states[t.b];
     for (int d = lane; d < kDigits; d += 64) {
         const int64_t dv = w.merged[d];
         if (dv)
-            atomicAdd((unsigned long long *)&st->digit[d], (unsigned long long)dv);
+            __hip_atomic_fetch_add(&st->digit[d], dv, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (lane == 0 && spec)
-        atomicOr(&st->special, spec);
-    __threadfence();
+        __hip_atomic_fetch_or(&st->special, spec, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_SYSTEM);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
     uint32_t ticket = 0;
     if (lane == 0)
-        ticket = atomicAdd(&st->ticket, 1u);
+        ticket = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_SYSTEM);
     ticket = __shfl(ticket, 0, 64);
     if (ticket == t.nchunks - 1) {
-        __threadfence();
         const int of = out_mode == XSUM_SAME ? LaneOut<FMT>::kNatural : out_mode;
         Finish fin{kRound, of, out + s, flags ? flags + s : nullptr, 1};
-        finish_state<false>(st, fin, lane);
+        finish_state<true>(st, fin, lane);
     }
 }
 
