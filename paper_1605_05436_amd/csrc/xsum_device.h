@@ -83,6 +83,12 @@ __device__ __forceinline__ void lds_add(uint64_t *p, uint64_t v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The same for a 32-bit entry (ds_add_u32).
+__device__ __forceinline__ void lds_add(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ uint64_t lds_load(uint64_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -91,6 +97,26 @@ __device__ __forceinline__ uint64_t lds_load(uint64_t *p)
 __device__ __forceinline__ void lds_store(uint64_t *p, uint64_t v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t lds_load(uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_store(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void wave_lds_fence()
+{
+    // every LDS operation of this wave issued so far has completed and is
+    // ordered before what follows (other lanes' column entries are read
+    // next).  The fence names LDS only, so loads and atomics in flight to
+    // global memory are not waited for.
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Special-value bits of a state: bit 0 NaN, bit 1 +inf, bit 2 -inf.
@@ -137,11 +163,13 @@ __device__ __forceinline__ void add_f32(uint32_t b, uint64_t *col,
 }
 
 // Two bfloat16 elements (the halves of w) into the lane's column; amax keeps
-// the largest magnitude bits seen in each half.
+// the largest magnitude bits seen in each half.  The column's entries are
+// 64-bit, or 32-bit (C = uint32_t) in the single-sum kernel, which then
+// flushes them before 2^17 chunks can reach one entry.
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void add_bf16_pair(uint32_t w, uint64_t *col,
-                                              u16x2 &amax)
+template <typename C>
+__device__ __forceinline__ void add_bf16_pair(uint32_t w, C *col, u16x2 &amax)
 {
     const u16x2 h = __builtin_bit_cast(u16x2, w);
     const u16x2 a = h & (u16x2)0x7fffu;
@@ -150,18 +178,20 @@ __device__ __forceinline__ void add_bf16_pair(uint32_t w, uint64_t *col,
     const u16x2 u = __builtin_elementwise_max(a, (u16x2)0x80u) + (u16x2)0x200u;
     const u16x2 m = (a & (u16x2)0x7fu) | __builtin_elementwise_min(a, (u16x2)0x80u);
     const u16x2 t = m << ((u >> (u16x2)7) & (u16x2)7);   // < 2^15
-    // byte offset of entry 2 (q >> 3) + sign (entries are 512 bytes apart):
-    // q >> 3 sits in bits 10 to 15 of u, the sign goes to bit 9
-    const uint32_t off = (__builtin_bit_cast(uint32_t, u) & 0xfc00fc00u) |
-                         ((w >> 6) & 0x02000200u);
+    // byte offset of entry 2 (q >> 3) + sign: q >> 3 sits in bits 10 to 15
+    // of u.  64-bit entries are 512 bytes apart (sign to bit 9), 32-bit ones
+    // 256 bytes (everything one bit lower)
+    const uint32_t uu = __builtin_bit_cast(uint32_t, u);
+    const uint32_t off = sizeof(C) == 8
+                             ? (uu & 0xfc00fc00u) | ((w >> 6) & 0x02000200u)
+                             : ((uu >> 1) & 0x7e007e00u) | ((w >> 7) & 0x01000100u);
     char *base = (char *)col;
-    lds_add((uint64_t *)(base + (off & 0xffffu)), (uint64_t)t.x);
-    lds_add((uint64_t *)(base + (off >> 16)), (uint64_t)t.y);
+    lds_add((C *)(base + (off & 0xffffu)), (C)t.x);
+    lds_add((C *)(base + (off >> 16)), (C)t.y);
 }
 
-template <int FMT>
-__device__ __forceinline__ void add_vec(const vec4u &q, uint64_t *col,
-                                        uint32_t &emax)
+template <int FMT, typename C>
+__device__ __forceinline__ void add_vec(const vec4u &q, C *col, uint32_t &emax)
 {
     if constexpr (FMT == XSUM_F64) {
         add_f64(q.x, q.y, col, emax);
@@ -205,8 +235,8 @@ __device__ __forceinline__ void fix_f32(uint32_t b, uint64_t *col,
 
 // The same for the two bfloat16 halves of w: the special halves are added
 // again with the opposite sign, the others are replaced by +0 (which adds 0).
-__device__ __forceinline__ void fix_bf16_pair(uint32_t w, uint64_t *col,
-                                              uint32_t &spec)
+template <typename C>
+__device__ __forceinline__ void fix_bf16_pair(uint32_t w, C *col, uint32_t &spec)
 {
     uint32_t neg = 0;
 #pragma unroll
@@ -223,9 +253,8 @@ __device__ __forceinline__ void fix_bf16_pair(uint32_t w, uint64_t *col,
     }
 }
 
-template <int FMT>
-__device__ __forceinline__ void fix_vec(const vec4u &q, uint64_t *col,
-                                        uint32_t &spec)
+template <int FMT, typename C>
+__device__ __forceinline__ void fix_vec(const vec4u &q, C *col, uint32_t &spec)
 {
     if constexpr (FMT == XSUM_F64) {
         fix_f64(q.x, q.y, col, spec);
@@ -244,9 +273,8 @@ __device__ __forceinline__ void fix_vec(const vec4u &q, uint64_t *col,
 }
 
 // Add U vectors, then fix up the (rare) lanes that met a special value.
-template <int FMT, int U>
-__device__ __forceinline__ void add_tile(const vec4u (&q)[U], uint64_t *col,
-                                         uint32_t &spec)
+template <int FMT, int U, typename C>
+__device__ __forceinline__ void add_tile(const vec4u (&q)[U], C *col, uint32_t &spec)
 {
     uint32_t emax = 0;      // largest exponent field (binary64) or magnitude
 #pragma unroll
@@ -262,9 +290,8 @@ __device__ __forceinline__ void add_tile(const vec4u (&q)[U], uint64_t *col,
 }
 
 // One element read with a scalar load (unaligned head, ragged tail).
-template <int FMT>
-__device__ __forceinline__ void add_scalar(const uint8_t *p, uint64_t *col,
-                                           uint32_t &spec)
+template <int FMT, typename C>
+__device__ __forceinline__ void add_scalar(const uint8_t *p, C *col, uint32_t &spec)
 {
     uint32_t emax = 0;
     if constexpr (FMT == XSUM_F64) {
@@ -344,14 +371,13 @@ __device__ __forceinline__ void add_row(int64_t *blk, int d, uint64_t lo, int64_
 // and above in binary64 (and their carries), and of 2^125 and above in the
 // binned formats, so instead of a second pass each lane adds its own two top
 // entries, and only when one of them is non-zero anywhere in the wave.
-template <int FMT>
-__device__ __forceinline__ void merge_wave_columns(uint64_t (*cols)[64],
-                                                   int64_t *blk, int lane)
+template <int FMT, typename C>
+__device__ __forceinline__ void merge_wave_columns(C (*cols)[64], int64_t *blk, int lane)
 {
     using G = Geo<FMT>;
     static_assert(G::kN == 66, "two rows above the lanes");
     {
-        const uint64_t *row = cols[lane];
+        const C *row = cols[lane];
         uint64_t lo = 0;
         int64_t hi = 0;
 #pragma unroll 16

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "xsum.h"
 #include "xsum_device.h"
 #include "xsum_internal.h"
@@ -38,10 +40,14 @@ namespace xsum {
 // fewer than (kNormTiles + 2)*U*2 + 2 < 2047 elements, each adding below
 // 2^32 + 2^52 to a digit that started below 2^32: every entry stays below
 // 2^63 and its high word below 2^31 in magnitude, as the block merge assumes.
-// Binned (binary32, bfloat16) entries only grow.  The launcher gives every
-// block at most 2^24 tiles of U * kPerVec elements per lane (64 binary32, each
-// chunk below 2^31; 192 bfloat16, each below 2^15), so an entry stays below
-// 2^61 and its high word below 2^31, as the block merge assumes.
+// Binned (binary32, bfloat16) entries only grow.  binary32: the launcher
+// gives every block at most 2^24 tiles of U * kPerVec = 64 elements per lane,
+// each chunk below 2^31, so an entry stays below 2^61 and its high word below
+// 2^31, as the block merge assumes.  bfloat16 entries are 32-bit (half the
+// LDS, so twice the resident waves): chunks are below 2^15, and every
+// kFlushTiles tiles each wave merges its columns into the block vector and
+// clears them, so an entry receives fewer than (kFlushTiles + 2) * U * 8 + 2
+// < 2^17 chunks between clears.
 template <int FMT, int WAVES, int U, bool WAVE_CONTIG>
 __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
     const uint8_t *__restrict__ x, uint32_t head, uint64_t nvec,
@@ -53,15 +59,18 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
     constexpr int kNormTiles = 512 / U;
     static_assert(FMT != XSUM_F64 || (kNormTiles + 2) * U * 2 + 2 < 2047,
                   "binary64 column headroom");
-    static_assert(FMT == XSUM_F64 || (FMT == XSUM_F32 ? U * 4 <= 64 : U * 8 <= 192),
-                  "binned column headroom");
-    __shared__ uint64_t cols[WAVES][G::kN][64];
+    constexpr int kFlushTiles = 256;
+    static_assert(FMT != XSUM_F32 || U * 4 <= 64, "binary32 column headroom");
+    static_assert(FMT != XSUM_BF16 || (kFlushTiles + 2) * U * 8 + 2 < (1 << 17),
+                  "bfloat16 column headroom");
+    using ColT = std::conditional_t<FMT == XSUM_BF16, uint32_t, uint64_t>;
+    __shared__ ColT cols[WAVES][G::kN][64];
     __shared__ int64_t blk[kDigits];
     __shared__ uint32_t blk_spec;
     __shared__ int is_last;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint64_t *col = &cols[wave][0][lane];
+    ColT *col = &cols[wave][0][lane];
     // vector j of this thread within a tile: interleaved across the block, or
     // a contiguous 64*U-vector run per wave
     const uint64_t my0 = WAVE_CONTIG ? (uint64_t)wave * 64 * U + lane : (uint64_t)tid;
@@ -73,6 +82,7 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
         blk[d] = 0;
     if (tid == 0)
         blk_spec = 0;
+    __syncthreads();    // blk is zero before any wave flushes into it
     uint32_t spec = 0;
 
     const vec4u *v = (const vec4u *)(x + (uint64_t)head * G::kBytes);
@@ -110,6 +120,17 @@ __global__ __launch_bounds__(WAVES * 64) void accumulate_kernel(
                 since_norm += 2;
                 if (since_norm >= kNormTiles) {
                     normalise_column<G::kN>(col);
+                    since_norm = 0;
+                }
+            } else if constexpr (FMT == XSUM_BF16) {
+                since_norm += 2;
+                if (since_norm >= kFlushTiles) {
+                    wave_lds_fence();
+                    merge_wave_columns<FMT>(cols[wave], blk, lane);
+                    wave_lds_fence();
+#pragma unroll
+                    for (int d = 0; d < G::kN; ++d)
+                        col[d * 64] = 0;
                     since_norm = 0;
                 }
             }
@@ -233,11 +254,12 @@ int element_size(int dtype)
 }
 
 // Launch shapes (measured on MI355X with the timing harness, config-2-like
-// data): a column is 66 x 64 x 8 B = 33 KiB per wave in every format, so four
-// waves fill a CU's 160 KiB of LDS.  Each wave keeps U 16-byte loads per lane
-// in flight while it adds the previous U; wave-contiguous tiles give each wave
-// its own 64*U-vector stream.  bfloat16, with the most work per byte, runs
-// best as four one-wave blocks with deeper tiles.
+// data): a column is 66 x 64 x 8 B = 33 KiB per wave for binary64 and
+// binary32, so four waves fill a CU's 160 KiB of LDS; bfloat16's 32-bit
+// entries take half that, so eight one-wave blocks fit (two waves per SIMD).
+// Each wave keeps U 16-byte loads per lane in flight while it adds the
+// previous U; wave-contiguous tiles give each wave its own 64*U-vector
+// stream.
 template <int FMT> struct Shape_;
 template <> struct Shape_<XSUM_F64> {
     static constexpr int kWaves = 2, kUnroll = 16, kBlocksPerCu = 2;
@@ -248,7 +270,7 @@ template <> struct Shape_<XSUM_F32> {
     static constexpr bool kWaveContig = true;
 };
 template <> struct Shape_<XSUM_BF16> {
-    static constexpr int kWaves = 1, kUnroll = 24, kBlocksPerCu = 4;
+    static constexpr int kWaves = 1, kUnroll = 24, kBlocksPerCu = 8;
     static constexpr bool kWaveContig = true;
 };
 

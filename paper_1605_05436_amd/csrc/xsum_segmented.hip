@@ -47,16 +47,6 @@ struct WaveLds {
     int64_t merged[kDigits];
 };
 
-__device__ __forceinline__ void wave_lds_fence()
-{
-    // every LDS operation of this wave issued so far has completed and is
-    // ordered before what follows (other lanes' column entries are read
-    // next).  The fence names LDS only, so loads and atomics in flight to
-    // global memory (the next work item's records) are not waited for.
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup", "local");
-    __builtin_amdgcn_wave_barrier();
-}
-
 template <int FMT>
 __device__ __forceinline__ void zero_column(uint64_t *col)
 {
