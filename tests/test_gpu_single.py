@@ -120,6 +120,28 @@ def test_large_inputs_many_blocks(fmt, kind):
         assert state == bytes(576), blocks
 
 
+@pytest.mark.parametrize("pattern", ["positive", "negative", "alternating"])
+def test_bfloat16_column_flush(pattern):
+    """bfloat16 columns hold 32-bit entries that each wave clears into the
+    block vector every 256 tiles.  With one block, 2^23 copies of the value
+    whose chunk is the largest possible (significand all ones, shifted by 7)
+    put 682 tiles of chunks into the same entry: without the flushes the
+    entry would overflow after 2^17 of them."""
+    n = 1 << 23
+    bits = np.full(n, 0x41ff, dtype=np.uint16)          # 31.875: exponent 131, (131+4) & 7 == 7
+    if pattern == "negative":
+        bits |= np.uint16(0x8000)
+    elif pattern == "alternating":
+        bits[1::2] |= np.uint16(0x8000)
+        bits[-1] = np.uint16(0x3f80)                    # and a 1.0 so the sum is not zero
+    ref = want(bits, "bf16")
+    t = to_device(bits)
+    for blocks in (1, 0):
+        v, f, state = gpu_sum_async(t, n, "bf16", blocks=blocks)
+        assert (v, f) == ref, blocks
+        assert state == bytes(576)
+
+
 def test_specials_published_by_distant_blocks():
     """Special values seen by blocks far apart all reach the result; one
     scratch state serves calls of shrinking sizes, the empty sum included."""
