@@ -446,7 +446,7 @@ static __device__ __forceinline__ void normalise_wave(int64_t &a, int64_t &b, in
 {
     const bool top_lane = lane == 33;
     const bool live = lane <= 33;
-    // two local carry steps: |d| < 2^62 -> (-2^30, 2^32 + 2^30) -> [-1, 2^32]
+    // two local carry steps: |d| < 2^62 -> [-2^30, 2^32 + 2^30) -> [-1, 2^32]
 #pragma unroll
     for (int step = 0; step < 2; ++step) {
         const int64_t ca = a >> 32, cb = b >> 32;
