@@ -2,6 +2,8 @@
 // the segmented kernel (device).
 #pragma once
 
+#include <cstddef>
+
 #include <stdint.h>
 
 namespace xsum {
@@ -47,12 +49,16 @@ struct SegLane {
 // Control words at the start of the workspace.  Both return to zero at the
 // end of every launch (the last wave to finish resets them).
 struct SegCtl {
-    uint32_t head;   // next task to pop
-    uint32_t done;   // waves that found the queue empty
-    uint32_t pad[62];
+    uint32_t head;      // next task to pop
+    uint32_t done;      // waves that found the queue empty
+    uint32_t pad[58];
+    uint32_t zero[4];   // always zero: what a lane past its segment's end loads
 };
 
 static constexpr uint64_t kSegCtlBytes = sizeof(SegCtl);
+static_assert(sizeof(SegCtl) == 256 && offsetof(SegCtl, zero) % 16 == 0,
+              "control block: 256 bytes, a 16-byte-aligned zero vector");
+
 
 // One request chunk list of a serving batch (same layout as xsum_batch_item_t).
 struct BatchItem {

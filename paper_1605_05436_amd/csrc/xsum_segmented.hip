@@ -148,7 +148,8 @@ template <int FMT, int UL>
 __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLane &e,
                                                uint32_t count, uint32_t glog,
                                                uint64_t *col, int out_mode,
-                                               uint64_t *out, uint32_t *flags, int lane)
+                                               uint64_t *out, uint32_t *flags,
+                                               const vec4u *zero, int lane)
 {
     using G = Geo<FMT>;
     const uint32_t sub = (uint32_t)lane & ((1u << glog) - 1);
@@ -175,13 +176,16 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
     // each lane walks its share of its segment, UL vectors per step, the next
     // step's loads in flight while the current step is added
     vec4u qa[UL], qb[UL];
+    // Every lane loads on every step (no load sits in a branch, so the
+    // compiler's wait counts keep the spare buffer's loads in flight): a
+    // lane past the end of its share, or a step past the last, loads the
+    // zero vector instead.
     auto load_step = [&](vec4u (&q)[UL], uint32_t it) {
 #pragma unroll
         for (int j = 0; j < UL; ++j) {
             const uint64_t i = (uint64_t)it * UL + j;
-            q[j] = vec4u{0u, 0u, 0u, 0u};
-            if (i < my_nv)
-                q[j] = vp[i << glog];   // cached: neighbouring loads share lines
+            const vec4u *src = i < my_nv ? vp + (i << glog) : zero;
+            q[j] = *src;    // cached: neighbouring loads share lines
         }
     };
     auto norm_step = [&]() {
@@ -192,17 +196,17 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
             }
         }
     };
+    // as in accumulate_span, the spare buffer is loaded on every pass (past
+    // the last step, with zeros, never added)
     if (iters > 0)
         load_step(qa, 0);
     for (uint32_t it = 0; it < iters; it += 2) {
-        if (it + 1 < iters)
-            load_step(qb, it + 1);
+        load_step(qb, it + 1);
         add_tile<FMT, UL>(qa, col, spec);
         norm_step();
         if (it + 1 >= iters)
             break;
-        if (it + 2 < iters)
-            load_step(qa, it + 2);
+        load_step(qa, it + 2);
         add_tile<FMT, UL>(qb, col, spec);
         norm_step();
     }
@@ -262,26 +266,32 @@ __device__ __forceinline__ void accumulate_span(const vec4u *vp, uint64_t nv,
     const uint64_t full = nv / kTile;
     int since = 0;
     if (full > 0) {
+        // The next tile's loads are issued on every pass: past the span's
+        // last full tile every one of them re-reads the lane's vector of the
+        // tile just loaded (a cache hit) into the spare buffer, which is
+        // never added.  With no load skipped, the compiler's wait counts
+        // leave the spare buffer's loads in flight while the current tile is
+        // added; a skipped load would force a wait for every load issued.
         vec4u qa[UC], qb[UC];
 #pragma unroll
         for (int j = 0; j < UC; ++j)
             qa[j] = __builtin_nontemporal_load(vp + j * 64 + lane);
         for (uint64_t tt = 0; tt < full; tt += 2) {
             const bool more_b = tt + 1 < full;
-            if (more_b) {
+            const vec4u *pb = vp + (more_b ? tt + 1 : tt) * kTile + lane;
+            const uint64_t sb = more_b ? 64 : 0;
 #pragma unroll
-                for (int j = 0; j < UC; ++j)
-                    qb[j] = __builtin_nontemporal_load(vp + (tt + 1) * kTile + j * 64 + lane);
-            }
+            for (int j = 0; j < UC; ++j)
+                qb[j] = __builtin_nontemporal_load(pb + j * sb);
             add_tile<FMT, UC>(qa, col, spec);
             if (!more_b)
                 break;
             const bool more_a = tt + 2 < full;
-            if (more_a) {
+            const vec4u *pa = vp + (more_a ? tt + 2 : tt + 1) * kTile + lane;
+            const uint64_t sa = more_a ? 64 : 0;
 #pragma unroll
-                for (int j = 0; j < UC; ++j)
-                    qa[j] = __builtin_nontemporal_load(vp + (tt + 2) * kTile + j * 64 + lane);
-            }
+            for (int j = 0; j < UC; ++j)
+                qa[j] = __builtin_nontemporal_load(pa + j * sa);
             add_tile<FMT, UC>(qb, col, spec);
             if constexpr (FMT == XSUM_F64) {
                 since += 2;
@@ -505,11 +515,14 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
         if (kind == kLaneGroup) {
             const uint32_t glog = t.kind_dtype_flags >> 16;
             if (dtype == XSUM_F64)
-                run_lane_group<XSUM_F64, UL>(base, e, t.b, glog, col, out_mode, out, flags, lane);
+                run_lane_group<XSUM_F64, UL>(base, e, t.b, glog, col, out_mode, out, flags,
+                                              (const vec4u *)ctl->zero, lane);
             else if (dtype == XSUM_F32)
-                run_lane_group<XSUM_F32, UL>(base, e, t.b, glog, col, out_mode, out, flags, lane);
+                run_lane_group<XSUM_F32, UL>(base, e, t.b, glog, col, out_mode, out, flags,
+                                              (const vec4u *)ctl->zero, lane);
             else
-                run_lane_group<XSUM_BF16, UL>(base, e, t.b, glog, col, out_mode, out, flags, lane);
+                run_lane_group<XSUM_BF16, UL>(base, e, t.b, glog, col, out_mode, out, flags,
+                                              (const vec4u *)ctl->zero, lane);
         } else if (kind == kWhole) {
             if (dtype == XSUM_F64)
                 run_whole<XSUM_F64, UC>(base, t, w, col, out_mode, out, flags, lane);
