@@ -14,6 +14,9 @@ its error against the exact result), and the CPU oracle timed on the host.
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 
 Other workloads (reported separately, not the headline line):
+    python bench.py --dtype f32            the same 2 GiB as 2^29 binary32
+                                           (cancelling pairs + perturbations)
+    python bench.py --dtype bf16           2 GiB as 2^30 bfloat16 (mixed signs)
     python bench.py --workload segmented   10^6 lognormal segments, mixed
                                            formats, one graph-captured launch
     python bench.py --workload serving     Poisson 2000 req/s for 60 s,
