@@ -248,11 +248,12 @@ typedef struct xsum_segment {
  *                 16384 / 32768 for binary64 / binary32 / bfloat16: 64 KiB of
  *                 input; at most 2^20 / 2^22 / 2^23)
  *   wave_max[d]   longer segments with at most this many elements are summed
- *                 whole by one wave (default: 4 MiB of input; values above
- *                 2^36 act as 2^36)
+ *                 whole by one wave (default: 1 MiB of input for binary64,
+ *                 4 MiB for binary32 and bfloat16; values above 2^36 act as
+ *                 2^36)
  *   chunk_vectors longer segments still are cut into chunks of this many
  *                 16-byte vectors, summed by separate waves whose states are
- *                 merged (default 2^18 = 4 MiB, range [64, 2^26])
+ *                 merged (default 2^16 = 1 MiB, range [64, 2^26])
  *   blocks_per_cu resident one-wave workgroups per compute unit (default 4,
  *                 range [1, 16])
  *   lane_buckets  per-lane segments are grouped by length in this many

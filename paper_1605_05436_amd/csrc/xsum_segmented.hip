@@ -694,6 +694,6 @@ hipError_t launch_segmented(const void *base, const SegDesc *segs,
     return hipGetLastError();
 }
 
-uint64_t segmented_chunk_vectors() { return 1ull << 18; }  // 4 MiB
+uint64_t segmented_chunk_vectors() { return 1ull << 16; }  // 1 MiB
 
 }  // namespace xsum
