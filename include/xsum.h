@@ -244,9 +244,10 @@ typedef struct xsum_segment {
 /* Tuning knobs of a plan, indexed by dtype d where per-format; 0 in any
  * field means the library default.
  *   lane_max[d]   segments with at most this many elements are summed by a
- *                 few lanes each, 16 to 64 segments to a wave (default 8192 /
- *                 16384 / 32768 for binary64 / binary32 / bfloat16: 64 KiB of
- *                 input; at most 2^20 / 2^22 / 2^23)
+ *                 few lanes each, 16 to 64 segments to a wave (default 16384 /
+ *                 16384 / 32768 for binary64 / binary32 / bfloat16: 128 KiB of
+ *                 binary64, 64 KiB of the narrow formats; at most 2^20 / 2^22
+ *                 / 2^23)
  *   wave_max[d]   longer segments with at most this many elements are summed
  *                 whole by one wave (default: 1 MiB of input for binary64,
  *                 4 MiB for binary32 and bfloat16; values above 2^36 act as

@@ -28,15 +28,15 @@ DEFAULT_CANDIDATES = [
     # (lane_max per dtype, wave_max per dtype, chunk_vectors, blocks_per_cu,
     #  lane_buckets, two_lanes_from, four_lanes_from); 0 = library default
     ((0, 0, 0), (0, 0, 0), 0, 0, 0, 0, 0),                  # library defaults
-    ((4096, 8192, 16384), (0, 0, 0), 0, 0, 4, 0, 0),
-    ((16384, 32768, 65536), (0, 0, 0), 0, 0, 4, 0, 0),
-    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 2, 0, 0),
-    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 8, 0, 0),
-    ((8192, 16384, 32768), (1 << 18, 1 << 19, 1 << 20), 1 << 17, 0, 4, 0, 0),
-    ((8192, 16384, 32768), (1 << 20, 1 << 21, 1 << 22), 1 << 19, 0, 4, 0, 0),
-    ((8192, 16384, 32768), (0, 0, 0), 0, 3, 4, 0, 0),
-    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 4, 1024, 8192),
-    ((8192, 16384, 32768), (0, 0, 0), 0, 0, 4, 4096, 1 << 40),
+    ((8192, 8192, 16384), (0, 0, 0), 0, 0, 0, 0, 0),        # half the lane limits
+    ((32768, 32768, 65536), (0, 0, 0), 0, 0, 0, 0, 0),      # twice them
+    ((0, 0, 0), (0, 0, 0), 0, 0, 2, 0, 0),
+    ((0, 0, 0), (0, 0, 0), 0, 0, 8, 0, 0),
+    ((0, 0, 0), (1 << 16, 1 << 19, 1 << 20), 1 << 15, 0, 0, 0, 0),
+    ((0, 0, 0), (1 << 19, 1 << 21, 1 << 22), 1 << 18, 0, 0, 0, 0),
+    ((0, 0, 0), (0, 0, 0), 0, 3, 0, 0, 0),
+    ((0, 0, 0), (0, 0, 0), 0, 0, 0, 1024, 8192),
+    ((0, 0, 0), (0, 0, 0), 0, 0, 0, 4096, 1 << 40),
 ]
 
 

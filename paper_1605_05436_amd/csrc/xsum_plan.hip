@@ -53,9 +53,11 @@ using xsum::api_hip_fail;
 
 constexpr int kPerVec[3] = {2, 4, 8};
 constexpr int kBytes[3] = {8, 4, 2};
-// Default per-lane limits: segments up to this many elements are summed one
-// per lane (64 KiB of input per lane).
-constexpr uint64_t kLaneMaxDefault[3] = {8192, 16384, 32768};
+// Default per-lane limits: segments up to this many elements are summed by
+// lane groups (128 KiB of binary64, 64 KiB of the narrow formats; binary64
+// segments of 64-128 KiB measured about 1% faster there than as whole-wave
+// items).
+constexpr uint64_t kLaneMaxDefault[3] = {16384, 16384, 32768};
 // segment sizes (bytes) from which lane groups give a segment two or four lanes
 constexpr uint64_t kTwoLanesFromDefault = 2048, kFourLanesFromDefault = 32768;
 // Segments up to 1 MiB (binary64) or 4 MiB (binary32, bfloat16) are summed
