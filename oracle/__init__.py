@@ -35,11 +35,13 @@ from .ieee import (FORMATS, UNIT_EXP, FLAG_INEXACT, FLAG_OVERFLOW, FLAG_NAN,
                    FLAG_INF, Format, decode, round_to_format, fmt_of)
 from .exact import (ExactSum, exact_sum, finish, oracle_sum, fraction_sum,
                     fraction_to_format, value_fraction)
-from .binned import exact_sum_binned, oracle_sum_binned, build_binned
+from .binned import (exact_sum_binned, oracle_sum_binned, build_binned,
+                     segmented_exact_sums, segmented_oracle_sums)
 
 __all__ = [
     "FORMATS", "UNIT_EXP", "FLAG_INEXACT", "FLAG_OVERFLOW", "FLAG_NAN",
     "FLAG_INF", "Format", "decode", "round_to_format", "fmt_of", "ExactSum",
     "exact_sum", "finish", "oracle_sum", "fraction_sum", "fraction_to_format",
     "value_fraction", "exact_sum_binned", "oracle_sum_binned", "build_binned",
+    "segmented_exact_sums", "segmented_oracle_sums",
 ]

@@ -104,3 +104,66 @@ def oracle_sum_binned(x, fmt, out_fmt=None, threads=None):
         out_fmt = "f32" if f.name == "bf16" else f.name
     acc, _ = exact_sum_binned(x, f, threads)
     return finish(acc, out_fmt)
+
+
+SEG_LIMBS = 40   # 64-bit limbs per segment total written by bins.c
+
+
+def _load_segmented():
+    lib = _load()
+    if not hasattr(lib, "_seg_ready"):
+        lib.oracle_segmented_sums.restype = ctypes.c_int
+        lib.oracle_segmented_sums.argtypes = [
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+        lib._seg_ready = True
+    return lib
+
+
+def segmented_exact_sums(buf, byte_offset, length, fmt_code, threads=None):
+    """Exact states of many segments of one byte buffer.
+
+    Segment i is length[i] elements of format fmt_code[i] (0 binary64,
+    1 binary32, 2 bfloat16) starting byte_offset[i] bytes into buf (a numpy
+    array, read as bytes).  Each segment is summed by the exponent bins of
+    ``bins.c`` and folded there into one wide two's-complement integer, which
+    becomes a Python int here.  Returns a list of ``ExactSum``.
+    """
+    raw = np.ascontiguousarray(np.asarray(buf).reshape(-1)).view(np.uint8)
+    off = np.ascontiguousarray(byte_offset, dtype=np.uint64)
+    ln = np.ascontiguousarray(length, dtype=np.uint64)
+    fc = np.ascontiguousarray(fmt_code, dtype=np.uint32)
+    nseg = len(off)
+    if not (len(ln) == nseg and len(fc) == nseg):
+        raise ValueError("segment arrays differ in length")
+    esize = np.array([8, 4, 2], dtype=np.uint64)
+    if nseg and (fc.max() > 2 or np.any(off + ln * esize[np.minimum(fc, 2)] > raw.size)):
+        raise ValueError("segment outside the buffer or unknown format")
+    limbs = np.zeros(nseg * SEG_LIMBS, dtype=np.uint64)
+    special = np.zeros(max(nseg, 1), dtype=np.uint32)
+    nthr = default_threads() if threads is None else int(threads)
+    used = _load_segmented().oracle_segmented_sums(
+        raw.ctypes.data if raw.size else None, off.ctypes.data, ln.ctypes.data,
+        fc.ctypes.data, nseg, nthr, limbs.ctypes.data, special.ctypes.data)
+    if used < 0:
+        raise RuntimeError("oracle_segmented_sums rejected its arguments")
+    data = limbs.tobytes()
+    step = SEG_LIMBS * 8
+    out = []
+    sp = special.tolist()
+    for i in range(nseg):
+        total = int.from_bytes(data[i * step:(i + 1) * step], "little", signed=True)
+        s = sp[i]
+        out.append(ExactSum(total, bool(s & 1), bool(s & 2), bool(s & 4)))
+    return out
+
+
+def segmented_oracle_sums(buf, byte_offset, length, fmt_code, out_fmt=None,
+                          threads=None):
+    """Correctly rounded (RNE) result (bits, flags) of every segment; the
+    output format defaults to binary64 for binary64 segments and binary32
+    for the others."""
+    names = ["f64", "f32", "f32"]
+    accs = segmented_exact_sums(buf, byte_offset, length, fmt_code, threads)
+    fc = np.asarray(fmt_code).tolist()
+    return [tuple(finish(a, out_fmt or names[c])) for a, c in zip(accs, fc)]

@@ -147,3 +147,173 @@ int oracle_binned_sum(const void *x, uint64_t n, int fmt, int nthreads,
     free(tids);
     return nthreads;
 }
+
+/*
+ * Per-segment exact sums (many independent sums over one buffer), for
+ * checking every segment of a large segmented batch.
+ *
+ * Segment i holds length[i] elements of format fmt[i] starting byte_off[i]
+ * bytes into base.  Each segment is accumulated into exponent bins exactly as
+ * above, and its bins are then folded into one wide two's-complement integer
+ * in units of 2^-1074 (the fixed-point number of Section 2):
+ *
+ *     total = sum_E bin[E] * 2^q(E),  q(E) = max(E,1) - 1         (binary64)
+ *                                      q(E) = max(E,1) + 924       (binary32)
+ *
+ * written to out_limbs[i * ORACLE_SEG_LIMBS ...] as little-endian 64-bit
+ * limbs.  ORACLE_SEG_LIMBS limbs (2560 bits) hold any total of at most 2^40
+ * finite inputs: |total| < 2^40 * 2^1024 * 2^1074.  special[i] gets the
+ * special-value bits.  Threads take interleaved segments.
+ */
+#define ORACLE_SEG_LIMBS 40
+
+typedef struct {
+    const uint8_t *base;
+    const uint64_t *byte_off, *length;
+    const uint32_t *fmt;
+    uint64_t nseg, first, stride;
+    uint64_t *out_limbs;
+    uint32_t *special;
+} seg_job_t;
+
+/* limbs += v * 2^s (two's complement over ORACLE_SEG_LIMBS limbs) */
+static void add_shifted(uint64_t *limbs, __int128 v, unsigned s)
+{
+    unsigned k = s / 64, r = s % 64;
+    /* v * 2^r as a sign-extended 192-bit value: three limbs */
+    unsigned __int128 u = (unsigned __int128)v;
+    uint64_t w0 = (uint64_t)(u << r);
+    uint64_t w1 = (uint64_t)((u << r) >> 64);
+    uint64_t w2 = r ? (uint64_t)(int64_t)(v >> (128 - r)) : (uint64_t)(v < 0 ? -1 : 0);
+    uint64_t ext = v < 0 ? ~0ull : 0ull;
+    uint64_t carry = 0;
+    for (unsigned j = k; j < ORACLE_SEG_LIMBS; ++j) {
+        uint64_t add = j == k ? w0 : j == k + 1 ? w1 : j == k + 2 ? w2 : ext;
+        unsigned __int128 t = (unsigned __int128)limbs[j] + add + carry;
+        limbs[j] = (uint64_t)t;
+        carry = (uint64_t)(t >> 64);
+    }
+}
+
+static void *seg_worker(void *arg)
+{
+    seg_job_t *j = (seg_job_t *)arg;
+    __int128 *bins = (__int128 *)calloc(2048, sizeof(__int128));
+    if (!bins)
+        return (void *)1;
+    for (uint64_t s = j->first; s < j->nseg; s += j->stride) {
+        int lo = 2048, hi = -1;
+        uint32_t sp = 0;
+        const uint64_t n = j->length[s];
+        const int fmt = (int)j->fmt[s];
+        const uint8_t *p = j->base + j->byte_off[s];
+        for (uint64_t i = 0; i < n; ++i) {
+            unsigned e;
+            int64_t m;
+            int neg;
+            if (fmt == ORACLE_F64) {
+                uint64_t b;
+                memcpy(&b, p + 8 * i, 8);
+                e = (unsigned)(b >> 52) & 0x7ffu;
+                uint64_t mf = b & ((1ull << 52) - 1);
+                neg = (int)(b >> 63);
+                if (e == 0x7ffu) {
+                    sp |= mf ? 1u : (neg ? 4u : 2u);
+                    continue;
+                }
+                m = (int64_t)(mf | (e ? (1ull << 52) : 0));
+            } else {
+                uint32_t b;
+                if (fmt == ORACLE_F32) {
+                    memcpy(&b, p + 4 * i, 4);
+                } else {
+                    uint16_t h;
+                    memcpy(&h, p + 2 * i, 2);
+                    b = (uint32_t)h << 16;
+                }
+                e = (b >> 23) & 0xffu;
+                uint32_t mf = b & ((1u << 23) - 1);
+                neg = (int)(b >> 31);
+                if (e == 0xffu) {
+                    sp |= mf ? 1u : (neg ? 4u : 2u);
+                    continue;
+                }
+                m = (int64_t)(mf | (e ? (1u << 23) : 0));
+            }
+            bins[e] += neg ? -(__int128)m : (__int128)m;
+            if ((int)e < lo)
+                lo = (int)e;
+            if ((int)e > hi)
+                hi = (int)e;
+        }
+        uint64_t *limbs = j->out_limbs + s * ORACLE_SEG_LIMBS;
+        memset(limbs, 0, ORACLE_SEG_LIMBS * sizeof(uint64_t));
+        for (int e = lo; e <= hi; ++e) {
+            if (bins[e]) {
+                unsigned emin1 = e ? (unsigned)e : 1u;
+                unsigned q = fmt == ORACLE_F64 ? emin1 - 1 : emin1 + 924;
+                add_shifted(limbs, bins[e], q);
+                bins[e] = 0;
+            }
+        }
+        j->special[s] = sp;
+    }
+    free(bins);
+    return NULL;
+}
+
+/*
+ * Returns the number of threads used, or -1 on a bad argument (an unknown
+ * format, a length above 2^40) or allocation failure.
+ */
+int oracle_segmented_sums(const void *base, const uint64_t *byte_off,
+                          const uint64_t *length, const uint32_t *fmt,
+                          uint64_t nseg, int nthreads, uint64_t *out_limbs,
+                          uint32_t *special)
+{
+    if (nseg > 0 && (byte_off == NULL || length == NULL || fmt == NULL ||
+                     out_limbs == NULL || special == NULL))
+        return -1;
+    for (uint64_t s = 0; s < nseg; ++s) {
+        if (fmt[s] > ORACLE_BF16 || length[s] > (1ull << 40))
+            return -1;
+        if (length[s] > 0 && base == NULL)
+            return -1;
+    }
+    if (nthreads < 1)
+        nthreads = 1;
+    if ((uint64_t)nthreads > nseg)
+        nthreads = nseg ? (int)nseg : 1;
+    seg_job_t *jobs = (seg_job_t *)calloc((size_t)nthreads, sizeof(seg_job_t));
+    pthread_t *tids = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    char *running = (char *)calloc((size_t)nthreads, 1);
+    int bad = 0;
+    if (!jobs || !tids || !running) {
+        free(jobs);
+        free(tids);
+        free(running);
+        return -1;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (seg_job_t){(const uint8_t *)base, byte_off, length, fmt, nseg,
+                              (uint64_t)t, (uint64_t)nthreads, out_limbs, special};
+    }
+    for (int t = 1; t < nthreads; ++t) {
+        if (pthread_create(&tids[t], NULL, seg_worker, &jobs[t]) == 0)
+            running[t] = 1;
+        else
+            bad |= seg_worker(&jobs[t]) != NULL;
+    }
+    bad |= seg_worker(&jobs[0]) != NULL;
+    for (int t = 1; t < nthreads; ++t) {
+        if (running[t]) {
+            void *rv = NULL;
+            pthread_join(tids[t], &rv);
+            bad |= rv != NULL;
+        }
+    }
+    free(jobs);
+    free(tids);
+    free(running);
+    return bad ? -1 : nthreads;
+}

@@ -16,10 +16,12 @@
 //     global memory and no device-scope fence.
 //   * chunk: a contiguous run of a very long segment, loaded coalesced by a
 //     wave.  The wave merges its 64 columns and adds the digits into the
-//     segment's state with int64 atomics; a per-segment ticket lets the last
-//     chunk round the state (and zero it for the next launch).  The ticket
-//     needs device-scope fences, which on this part write back and invalidate
-//     L2, so chunks are large and rare.
+//     segment's state with system-scope int64 atomics, which are performed
+//     at the memory side past every XCD's L2; after they have completed it
+//     takes a per-segment ticket, and the last chunk rounds the state (and
+//     zeroes it for the next launch).  No cache write-back is needed, but
+//     every chunk still pays a merge, its atomics and a ticket, so chunks
+//     are large.
 // The queue head and the exit counter return to zero at the end of every
 // launch, so a launch can be replayed from a captured graph without memsets.
 #include <hip/hip_runtime.h>

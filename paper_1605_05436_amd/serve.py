@@ -29,6 +29,7 @@ import numpy as np
 from . import (F64, F32, BF16, SAME, batch_item_dtype, xsum_batch_add,
                xsum_batch_finalize, xsum_batch_item_tasks, new_states,
                stream_handle)
+from .arena import ArenaAllocator
 
 ITEMSIZE = {F64: 8, F32: 4, BF16: 2}
 NATURAL_OUT = {F64: F64, F32: F32, BF16: F32}
@@ -50,38 +51,7 @@ class Request:
     slot: int = None
     arena_off: int = None
     pieces: deque = field(default_factory=deque)
-
-
-class ArenaAllocator:
-    """First-fit allocator over [0, size) with 256-byte granularity."""
-
-    def __init__(self, size, align=256):
-        self.align = align
-        self.free = [(0, size)]          # sorted (offset, length)
-
-    def alloc(self, nbytes):
-        need = max(self.align, (nbytes + self.align - 1) // self.align * self.align)
-        for i, (off, ln) in enumerate(self.free):
-            if ln >= need:
-                if ln == need:
-                    self.free.pop(i)
-                else:
-                    self.free[i] = (off + need, ln - need)
-                return off, need
-        return None, need
-
-    def release(self, off, ln):
-        free = self.free
-        free.append((off, ln))
-        free.sort()
-        merged = [free[0]]
-        for o, l in free[1:]:
-            po, pl = merged[-1]
-            if po + pl == o:
-                merged[-1] = (po, pl + l)
-            else:
-                merged.append((o, l))
-        self.free = merged
+    ready_event: object = None   # the payload is complete once this has fired
 
 
 class ExactSumServer:
@@ -92,6 +62,12 @@ class ExactSumServer:
     piece_elems   requests are cut into pieces of at most this many elements
     batch_bytes   byte budget of one batch (pieces of several requests)
     chunk_vectors 16-byte vectors per GPU work item inside a piece
+
+    Streams: the server works on its own compute and copy streams.  At
+    construction they wait for the caller's current stream (where the states
+    were zeroed); each request's admission copy waits for the stream it was
+    submitted from (see submit), and the payload tensor is recorded on the
+    copy stream so the caching allocator does not reuse it early.
     """
 
     def __init__(self, arena_bytes=4 << 30, slots=4096, piece_elems=1 << 24,
@@ -110,6 +86,11 @@ class ExactSumServer:
         self.ctl = torch.zeros(32, dtype=torch.int64, device=dev)
         self.compute = torch.cuda.Stream()
         self.copy = torch.cuda.Stream()
+        # the states and the control block were zeroed on the caller's
+        # stream; the server's own streams start after that work
+        here = torch.cuda.current_stream()
+        self.compute.wait_stream(here)
+        self.copy.wait_stream(here)
         self.piece_elems = piece_elems - piece_elems % 8   # keep 16-byte pieces
         self.batch_bytes = batch_bytes
         self.chunk_vectors = chunk_vectors
@@ -139,12 +120,19 @@ class ExactSumServer:
         self.elements = 0
 
     # ------------------------------------------------------------ admission --
-    def submit(self, req):
+    def submit(self, req, stream=None):
+        """Queue a request.  Its payload may still be in production on
+        `stream` (default: the caller's current stream); the admission copy
+        waits for everything enqueued there up to this call, so the caller
+        must not write req.src after submitting it."""
         nbytes = req.n * ITEMSIZE[req.dtype]
         if nbytes > self.arena.numel():
             raise ValueError("request %d needs %d bytes, more than the whole arena "
                              "(%d bytes); it could never be admitted"
                              % (req.rid, nbytes, self.arena.numel()))
+        ready = self.torch.cuda.Event()
+        ready.record(stream if stream is not None else self.torch.cuda.current_stream())
+        req.ready_event = ready
         self.waiting.append(req)
 
     def _admit(self, now):
@@ -161,8 +149,10 @@ class ExactSumServer:
             req.admitted = now
             if nbytes:
                 src = req.src.view(torch.uint8).reshape(-1)[:nbytes]
+                self.copy.wait_event(req.ready_event)
                 with torch.cuda.stream(self.copy):
                     self.arena[off:off + nbytes].copy_(src, non_blocking=True)
+                req.src.record_stream(self.copy)
             ev = torch.cuda.Event()
             ev.record(self.copy)
             req.copy_event = ev

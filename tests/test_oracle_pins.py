@@ -379,6 +379,64 @@ def test_binned_matches_plain_loop(fmt):
         assert (a.total, a.nan, a.pinf, a.ninf) == (b.total, b.nan, b.pinf, b.ninf)
 
 
+def _segment_buffer(rng, specs):
+    """A byte buffer holding segments of the given (format, bit patterns),
+    each at an element-aligned offset after a random gap."""
+    chunks, offs, lens, fmts = [], [], [], []
+    at = 0
+    for fc, bits in specs:
+        esize = [8, 4, 2][fc]
+        gap = int(rng.integers(0, 5)) * esize
+        at += gap
+        chunks.append(np.zeros(gap, dtype=np.uint8))
+        raw = bits.view(np.uint8)
+        offs.append(at)
+        lens.append(len(bits))
+        fmts.append(fc)
+        chunks.append(raw)
+        at += raw.size
+    return np.concatenate(chunks) if chunks else np.zeros(0, np.uint8), offs, lens, fmts
+
+
+def test_segmented_sums_match_plain_loop_per_segment():
+    # every bit pattern of every format, specials included, at full exponent
+    # range: the C fold into wide limbs must give the plain loop's integer
+    rng = np.random.default_rng(21)
+    width = [64, 32, 16]
+    dts = [np.uint64, np.uint32, np.uint16]
+    specs = []
+    for i in range(60):
+        fc = i % 3
+        n = int(rng.integers(0, 3000)) if i % 7 else 0
+        bits = rng.integers(0, 1 << width[fc], size=n, dtype=np.uint64).astype(dts[fc])
+        if i % 2 == 0:   # mostly finite
+            bits &= dts[fc](~(1 << (width[fc] - 2)) & ((1 << width[fc]) - 1))
+        specs.append((fc, bits))
+    # totals near both ends of the range: many +-DBL_MAX, subnormals only
+    specs.append((0, np.full(4096, 0x7FEFFFFFFFFFFFFF, dtype=np.uint64)))
+    specs.append((0, np.full(4097, 0xFFEFFFFFFFFFFFFF, dtype=np.uint64)))
+    specs.append((0, np.arange(1, 5000, dtype=np.uint64)))
+    specs.append((1, np.full(3000, 0xFF7FFFFF, dtype=np.uint32)))
+    buf, offs, lens, fmts = _segment_buffer(rng, specs)
+    got = oracle.segmented_exact_sums(buf, offs, lens, fmts, threads=3)
+    names = ["f64", "f32", "bf16"]
+    for (fc, bits), g in zip(specs, got):
+        a = oracle.exact_sum(bits, names[fc])
+        assert (g.total, g.nan, g.pinf, g.ninf) == (a.total, a.nan, a.pinf, a.ninf)
+    res = oracle.segmented_oracle_sums(buf, offs, lens, fmts, threads=2)
+    for (fc, bits), r in zip(specs, res):
+        assert r == tuple(oracle.oracle_sum(bits, names[fc]))
+
+
+def test_segmented_sums_reject_bad_segments():
+    buf = np.zeros(64, dtype=np.uint8)
+    with pytest.raises(ValueError):
+        oracle.segmented_exact_sums(buf, [0], [9], [0])        # past the end
+    with pytest.raises(ValueError):
+        oracle.segmented_exact_sums(buf, [0], [1], [3])        # unknown format
+    assert oracle.segmented_exact_sums(buf, [], [], []) == []
+
+
 # -------------------------------------------------------- planted mistakes --
 
 def test_planted_dropped_hidden_bit_is_caught(monkeypatch):

@@ -10,14 +10,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _serve_module():
-    # load serve.py's allocator without importing the GPU library binding
-    path = os.path.join(ROOT, "paper_1605_05436_amd", "serve.py")
-    src = open(path).read()
-    start = src.index("class ArenaAllocator:")
-    end = src.index("class ExactSumServer:")
-    ns = {}
-    exec(compile(src[start:end], path, "exec"), ns)
-    return ns["ArenaAllocator"]
+    # the allocator module has no imports, so it loads without the GPU library
+    path = os.path.join(ROOT, "paper_1605_05436_amd", "arena.py")
+    spec = importlib.util.spec_from_file_location("_xsum_arena", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.ArenaAllocator
 
 
 def test_first_fit_alloc_release_and_coalesce():
