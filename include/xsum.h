@@ -307,7 +307,7 @@ xsum_status_t xsum_plan_get_info(const xsum_plan_t *plan,
 
 /* Bytes of device workspace a run of this plan needs (control words plus one
  * 576-byte state per chunked segment). */
-size_t xsum_segmented_workspace_size(const xsum_plan_t *plan);
+size_t xsum_plan_workspace_size(const xsum_plan_t *plan);
 
 /* Zero a workspace (a fill kernel on `stream`, no memset).  Needed once after
  * allocation; every completed run leaves the workspace zeroed again.
@@ -321,7 +321,7 @@ xsum_status_t xsum_segmented_workspace_init(void *workspace, size_t ws_bytes,
  *   out        device, nseg 8-byte slots; slot i receives segment i's result
  *              bit pattern zero-extended to 64 bits
  *   flags      device, nseg uint32 (XSUM_FLAG_* per segment), may be NULL
- *   workspace  device, >= xsum_segmented_workspace_size(plan) bytes, zeroed
+ *   workspace  device, >= xsum_plan_workspace_size(plan) bytes, zeroed
  *              once by xsum_segmented_workspace_init; runs sharing a
  *              workspace must be ordered
  * The launch contains no memset and no host synchronisation, so it may be
@@ -340,10 +340,51 @@ xsum_status_t xsum_segmented_capture(const xsum_plan_t *plan, const void *base,
 xsum_status_t xsum_graph_launch(void *graph_exec, void *stream);
 void xsum_graph_destroy(void *graph_exec);
 
+/*
+ * One-shot segmented sums (Section 1's problem, once per segment; Section 6:
+ * each segment is a reducer's key, summed into its own superaccumulator and
+ * rounded once), without a plan object: the call plans with the default
+ * tuning, puts the plan in the caller's workspace and launches.
+ *   base       device, 16-byte aligned; segment i starts at base + offset_i
+ *   segs       nseg descriptors, in device or host memory
+ *   out_dtype  XSUM_SAME (binary64 for binary64 segments, binary32 for the
+ *              others) or one output format for every segment
+ *   out        device, nseg 8-byte slots (result bit pattern, zero-extended)
+ *   flags      device, nseg uint32, may be NULL
+ *   workspace  device, 256-byte aligned, at least
+ *              xsum_segmented_workspace_size(nseg, total elements) bytes (or
+ *              the exact need of this table, named in the error message); no
+ *              initialisation needed, the call zeroes what must start at zero
+ * Blocking on the host until the plan is in the workspace: it first waits
+ * for the work already queued on `stream` (which may produce the table or
+ * still use the workspace), then reads the table; the sums themselves run
+ * asynchronously on `stream`.  Not capturable into a graph (it
+ * synchronises); use xsum_segmented_plan + xsum_segmented_capture for
+ * repeated batches of the same shape, which also skips the planning.
+ * Errors: as xsum_segmented_plan, plus XSUM_EINVAL for NULL or misaligned
+ * pointers and a workspace that is too small.  nseg == 0 does nothing.
+ */
+xsum_status_t xsum_exact_sum_segmented(const void *base, const xsum_segment_t *segs,
+                                       uint64_t nseg, int out_dtype, void *out,
+                                       uint32_t *flags, void *workspace, size_t ws_bytes,
+                                       void *stream);
+
+/* Workspace bytes that suffice for xsum_exact_sum_segmented on any table of
+ * nseg segments holding total_elems elements in all (an upper bound: control
+ * words, one state per possible chunked segment, the segment table, the
+ * largest possible number of work items and the lane entries).  0 if nseg >=
+ * 2^31 or total_elems > 2^50. */
+size_t xsum_segmented_workspace_size(uint64_t nseg, uint64_t total_elems);
+
 /* ------------------------------------------------------------------------
  * Serving batches: one launch adds chunks of many requests into per-request
  * device states that persist across launches (continuous batching); a second
- * launch rounds the states of the requests that are complete.
+ * launch rounds the states of the requests that are complete.  This is
+ * Section 6's combine / reduce / post-process with the reducer state kept
+ * between launches: chunks of one request are combined into its
+ * superaccumulator by exact integer addition in any order and batch, and the
+ * post-process rounds it once, so a request's result does not depend on the
+ * batches it was cut into or the requests it shared them with.
  * ------------------------------------------------------------------------ */
 
 /* One request's contribution to a batch (32 bytes, in device memory).

@@ -32,10 +32,11 @@ EXPORTED = [
     "xsum_acc_add_host", "xsum_exact_sum_host", "xsum_state_encode",
     "xsum_state_decode",
     "xsum_segmented_plan", "xsum_plan_destroy", "xsum_plan_get_info",
-    "xsum_segmented_workspace_size", "xsum_segmented_workspace_init",
+    "xsum_plan_workspace_size", "xsum_segmented_workspace_size",
+    "xsum_exact_sum_segmented", "xsum_segmented_workspace_init",
     "xsum_segmented_run", "xsum_segmented_capture", "xsum_graph_launch",
     "xsum_graph_destroy", "xsum_batch_item_tasks", "xsum_batch_add",
-    "xsum_batch_finalize",
+    "xsum_batch_finalize", "xsum_probe_read", "xsum_probe_flush",
 ]
 
 # xsum_batch_item_t as a numpy record (32 bytes)
@@ -141,8 +142,13 @@ def _load():
     lib.xsum_plan_destroy.argtypes = [vp]
     lib.xsum_plan_get_info.restype = i32
     lib.xsum_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.xsum_plan_workspace_size.restype = ctypes.c_size_t
+    lib.xsum_plan_workspace_size.argtypes = [vp]
     lib.xsum_segmented_workspace_size.restype = ctypes.c_size_t
-    lib.xsum_segmented_workspace_size.argtypes = [vp]
+    lib.xsum_segmented_workspace_size.argtypes = [u64, u64]
+    lib.xsum_exact_sum_segmented.restype = i32
+    lib.xsum_exact_sum_segmented.argtypes = [vp, vp, u64, i32, vp, vp, vp,
+                                             ctypes.c_size_t, vp]
     lib.xsum_segmented_workspace_init.restype = i32
     lib.xsum_segmented_workspace_init.argtypes = [vp, ctypes.c_size_t, vp]
     lib.xsum_segmented_run.restype = i32
@@ -160,6 +166,10 @@ def _load():
     lib.xsum_batch_add.argtypes = [vp, ctypes.c_uint32, u64, u64, vp, vp, vp]
     lib.xsum_batch_finalize.restype = i32
     lib.xsum_batch_finalize.argtypes = [vp, vp, ctypes.c_uint32, vp, vp, vp, vp]
+    lib.xsum_probe_read.restype = i32
+    lib.xsum_probe_read.argtypes = [vp, u64, vp, vp]
+    lib.xsum_probe_flush.restype = i32
+    lib.xsum_probe_flush.argtypes = [vp, u64, ctypes.c_uint32, vp]
     return lib
 
 
@@ -314,8 +324,20 @@ def xsum_plan_get_info(plan):
     return d
 
 
-def xsum_segmented_workspace_size(plan):
-    return int(_lib.xsum_segmented_workspace_size(_p(plan)))
+def xsum_plan_workspace_size(plan):
+    return int(_lib.xsum_plan_workspace_size(_p(plan)))
+
+
+def xsum_segmented_workspace_size(nseg, total_elems):
+    return int(_lib.xsum_segmented_workspace_size(nseg, total_elems))
+
+
+def xsum_exact_sum_segmented(base, segs, nseg, out_dtype, out, flags, ws, ws_bytes,
+                             stream=0):
+    """One-shot segmented sums; segs is a device or host address of nseg
+    24-byte descriptors."""
+    _check(_lib.xsum_exact_sum_segmented(_p(base), _p(segs), nseg, out_dtype, _p(out),
+                                         _p(flags), _p(ws), ws_bytes, _p(stream)))
 
 
 def xsum_segmented_workspace_init(ws, nbytes, stream=0):
@@ -354,6 +376,17 @@ def xsum_batch_add(items, nitems, ntasks, chunk_vectors, states, ctl, stream=0):
 def xsum_batch_finalize(slots, fmts, n, states, out, flags, stream=0):
     _check(_lib.xsum_batch_finalize(_p(slots), _p(fmts), n, _p(states), _p(out),
                                     _p(flags), _p(stream)))
+
+
+def xsum_probe_read(x, nbytes, sink, stream=0):
+    """Measurement only: stream nbytes at x once (the binary64 kernel's
+    access pattern, no arithmetic)."""
+    _check(_lib.xsum_probe_read(_p(x), nbytes, _p(sink), _p(stream)))
+
+
+def xsum_probe_flush(buf, nbytes, value=0, stream=0):
+    """Measurement only: fill nbytes at buf with a 32-bit value."""
+    _check(_lib.xsum_probe_flush(_p(buf), nbytes, value, _p(stream)))
 
 
 # ----------------------------------------------------- torch marshalling --
@@ -399,7 +432,7 @@ class SegmentedSum:
         import torch
         self.plan = xsum_segmented_plan(segs, out_dtype, tuning)
         self.nseg = len(segs)
-        self.ws_bytes = max(8, xsum_segmented_workspace_size(self.plan))
+        self.ws_bytes = max(8, xsum_plan_workspace_size(self.plan))
         self.workspace = torch.empty(self.ws_bytes // 8 + 1, dtype=torch.int64, device=device)
         xsum_segmented_workspace_init(self.workspace.data_ptr(), self.ws_bytes,
                                       stream_handle(stream))

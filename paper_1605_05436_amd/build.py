@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libxsum.so")
 SOURCES = ["xsum_kernels.hip", "xsum_segmented.hip", "xsum_plan.hip", "xsum_api.hip",
-           "xsum_stream.hip", "xsum_state.hip"]
+           "xsum_stream.hip", "xsum_state.hip", "xsum_probe.hip"]
 HEADERS = ["xsum_device.h", "xsum_internal.h", "xsum_segmented.h", "xsum_host.h"]
 ARCH = os.environ.get("XSUM_OFFLOAD_ARCH", "gfx950")
 
@@ -34,22 +34,48 @@ def hipcc():
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose=False):
-    """Compile every HIP source into libxsum.so (always recompiles)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I" + INCLUDE, "-I" + CSRC] + \
-        [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
                          text=True)
     out = "\n".join(l for l in res.stdout.splitlines()
                     if "packed-fp32-ops" not in l and "--hip-link" not in l)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + out)
-    if verbose and out.strip():
-        print(out)
+    return res.returncode, out
+
+
+def build(verbose=False):
+    """Compile every HIP source into libxsum.so (always recompiles).  The
+    sources are compiled to objects in parallel, then linked."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(ROOT, "_build", "xsum.%d" % os.getpid())
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        jobs.append((obj, [hipcc()] + compile_flags + ["-I" + INCLUDE, "-I" + CSRC, "-c",
+                                                       os.path.join(CSRC, src), "-o", obj]))
+    workers = min(len(jobs), max(1, os.cpu_count() or 1), 8)
+    with ThreadPoolExecutor(workers) as pool:
+        results = list(pool.map(lambda j: _run(j[1]), jobs))
+    for (obj, cmd), (rc, out) in zip(jobs, results):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        if rc != 0:
+            raise RuntimeError("hipcc failed:\n" + out)
+        if verbose and out.strip():
+            print(out)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    link = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + \
+        [obj for obj, _ in jobs] + ["-o", tmp]
+    if verbose:
+        print(" ".join(link), flush=True)
+    rc, out = _run(link)
+    if rc != 0:
+        raise RuntimeError("hipcc link failed:\n" + out)
     os.replace(tmp, LIB)
+    for obj, _ in jobs:
+        os.remove(obj)
+    os.rmdir(objdir)
     return LIB
 
 

@@ -81,17 +81,19 @@ void free_plan(xsum_plan *p)
     delete p;
 }
 
-}  // namespace
+// A plan as built on the host, before its arrays are placed in device memory.
+struct HostPlan {
+    std::vector<xsum::SegTask> tasks;
+    std::vector<xsum::SegLane> lanes;
+    uint32_t nslots = 0;
+    uint32_t small_from = 0;
+    int blocks = 0;
+    xsum_plan_info_t info{};
+};
 
-extern "C" {
-
-xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
-                                  int out_dtype, const xsum_seg_tuning_t *tuning,
-                                  xsum_plan_t **plan_out)
+xsum_status_t make_plan(const xsum_segment_t *segs, uint64_t nseg, int out_dtype,
+                        const xsum_seg_tuning_t *tuning, int cus, HostPlan &hp)
 {
-    if (plan_out == nullptr)
-        return api_fail(XSUM_EINVAL, "plan_out is NULL");
-    *plan_out = nullptr;
     if (nseg > 0 && segs == nullptr)
         return api_fail(XSUM_EINVAL, "segment array is NULL with nseg > 0");
     if (nseg >= (1ull << 31))
@@ -258,17 +260,8 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
     if (tasks.size() >= (1ull << 31))
         return api_fail(XSUM_ERANGE, "too many work items");
 
-    int dev, cus;
-    xsum_status_t st = xsum::api_current_cus(&dev, &cus);
-    if (st != XSUM_OK)
-        return st;
-    xsum_plan *p = new xsum_plan();
-    p->device = dev;
-    p->nseg = nseg;
-    p->out_mode = out_dtype;
-    p->ntasks = (uint32_t)tasks.size();
-    p->nslots = slots;
-    p->blocks = xsum::segmented_blocks(cus, blocks_per_cu);
+    hp.nslots = slots;
+    hp.blocks = xsum::segmented_blocks(cus, blocks_per_cu);
     // Items are claimed one at a time while they are large (longest first is
     // what balances the waves) and several at a time once an item is below
     // 1/16 of a wave's share of the estimated work.
@@ -276,29 +269,81 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
         long double total = 0;
         for (const HostTask &h : tasks)
             total += (long double)h.cost;
-        const long double share = total / (long double)std::max(1, p->blocks);
+        const long double share = total / (long double)std::max(1, hp.blocks);
         uint32_t i = 0;
-        while (i < p->ntasks && (long double)tasks[i].cost * 16 >= share)
+        while (i < (uint32_t)tasks.size() && (long double)tasks[i].cost * 16 >= share)
             ++i;
-        p->small_from = i;
+        hp.small_from = i;
     }
-    p->info.nseg = nseg;
-    p->info.lane_segments = lane_ids[0].size() + lane_ids[1].size() + lane_ids[2].size();
-    p->info.wave_segments = wave_ids.size();
-    p->info.chunked_segments = chunk_ids.size();
-    p->info.chunks = nchunks_total;
-    p->info.work_items = tasks.size();
-    p->info.blocks = (uint32_t)p->blocks;
+    hp.info.nseg = nseg;
+    hp.info.lane_segments = lane_ids[0].size() + lane_ids[1].size() + lane_ids[2].size();
+    hp.info.wave_segments = wave_ids.size();
+    hp.info.chunked_segments = chunk_ids.size();
+    hp.info.chunks = nchunks_total;
+    hp.info.work_items = tasks.size();
+    hp.info.blocks = (uint32_t)hp.blocks;
     for (int d = 0; d < 3; ++d) {
-        p->info.lane_max[d] = lane_max[d];
-        p->info.wave_max[d] = wave_max[d];
+        hp.info.lane_max[d] = lane_max[d];
+        hp.info.wave_max[d] = wave_max[d];
     }
-    p->info.chunk_vectors = chunk_vectors;
-    p->info.workspace_bytes = xsum::kSegCtlBytes + (uint64_t)slots * sizeof(xsum_acc_t);
+    hp.info.chunk_vectors = chunk_vectors;
+    hp.info.workspace_bytes = xsum::kSegCtlBytes + (uint64_t)slots * sizeof(xsum_acc_t);
 
-    std::vector<xsum::SegTask> flat(tasks.size());
+    hp.tasks.resize(tasks.size());
     for (size_t i = 0; i < tasks.size(); ++i)
-        flat[i] = tasks[i].t;
+        hp.tasks[i] = tasks[i].t;
+    hp.lanes = std::move(lanes);
+    return XSUM_OK;
+}
+
+// Where the one-shot call puts a plan in the caller's workspace: control
+// words, chunk states, then the segment table, work items and lane entries,
+// each on a 256-byte boundary.
+struct OneshotLayout {
+    uint64_t segs, tasks, lanes, total;
+};
+
+OneshotLayout oneshot_layout(uint64_t nseg, uint64_t ntasks, uint64_t nlanes, uint64_t nslots)
+{
+    auto up = [](uint64_t v) { return (v + 255) & ~uint64_t(255); };
+    OneshotLayout L;
+    L.segs = up(xsum::kSegCtlBytes + nslots * sizeof(xsum_acc_t));
+    L.tasks = up(L.segs + nseg * sizeof(xsum::SegDesc));
+    L.lanes = up(L.tasks + ntasks * sizeof(xsum::SegTask));
+    L.total = L.lanes + nlanes * sizeof(xsum::SegLane);
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
+                                  int out_dtype, const xsum_seg_tuning_t *tuning,
+                                  xsum_plan_t **plan_out)
+{
+    if (plan_out == nullptr)
+        return api_fail(XSUM_EINVAL, "plan_out is NULL");
+    *plan_out = nullptr;
+    int dev, cus;
+    xsum_status_t st = xsum::api_current_cus(&dev, &cus);
+    if (st != XSUM_OK)
+        return st;
+    HostPlan hp;
+    st = make_plan(segs, nseg, out_dtype, tuning, cus, hp);
+    if (st != XSUM_OK)
+        return st;
+    xsum_plan *p = new xsum_plan();
+    p->device = dev;
+    p->nseg = nseg;
+    p->out_mode = out_dtype;
+    p->ntasks = (uint32_t)hp.tasks.size();
+    p->nslots = hp.nslots;
+    p->small_from = hp.small_from;
+    p->blocks = hp.blocks;
+    p->info = hp.info;
+    const std::vector<xsum::SegTask> &flat = hp.tasks;
+    const std::vector<xsum::SegLane> &lanes = hp.lanes;
     hipError_t e = hipSuccess;
     if (nseg)
         e = hipMalloc((void **)&p->d_segs, nseg * sizeof(xsum::SegDesc));
@@ -333,9 +378,95 @@ xsum_status_t xsum_plan_get_info(const xsum_plan_t *plan, xsum_plan_info_t *info
     return XSUM_OK;
 }
 
-size_t xsum_segmented_workspace_size(const xsum_plan_t *plan)
+size_t xsum_plan_workspace_size(const xsum_plan_t *plan)
 {
     return plan ? (size_t)plan->info.workspace_bytes : 0;
+}
+
+size_t xsum_segmented_workspace_size(uint64_t nseg, uint64_t total_elems)
+{
+    // With the default tuning a chunked segment is longer than the smallest
+    // wave_max and every chunk but its last covers chunk_vectors 16-byte
+    // vectors, so: states <= min(nseg, total / min_wave_max); work items <=
+    // nseg + total / min_chunk_elems.  Each array starts on a 256-byte
+    // boundary.
+    if (nseg >= (1ull << 31) || total_elems > (1ull << 50))
+        return 0;
+    const uint64_t min_wave = std::min(kWaveMaxDefault[0],
+                                       std::min(kWaveMaxDefault[1], kWaveMaxDefault[2]));
+    const uint64_t min_chunk = xsum::segmented_chunk_vectors() * 2;   // binary64
+    const uint64_t states = std::min<uint64_t>(nseg, total_elems / min_wave);
+    const uint64_t items = nseg + total_elems / min_chunk + 1;
+    return (size_t)(oneshot_layout(nseg, items, nseg, states).total);
+}
+
+xsum_status_t xsum_exact_sum_segmented(const void *base, const xsum_segment_t *segs,
+                                       uint64_t nseg, int out_dtype, void *out,
+                                       uint32_t *flags, void *workspace, size_t ws_bytes,
+                                       void *stream)
+{
+    if (nseg == 0)
+        return XSUM_OK;
+    if (segs == nullptr || base == nullptr || out == nullptr || workspace == nullptr)
+        return api_fail(XSUM_EINVAL, "segs, base, out or workspace is NULL");
+    if ((uintptr_t)base % 16 != 0)
+        return api_fail(XSUM_EINVAL, "base must be 16-byte aligned");
+    if ((uintptr_t)out % 8 != 0 || (uintptr_t)workspace % 256 != 0 ||
+        (flags && (uintptr_t)flags % 4 != 0))
+        return api_fail(XSUM_EINVAL, "misaligned out, flags or workspace (256 bytes)");
+    if (nseg >= (1ull << 31))
+        return api_fail(XSUM_ERANGE, "at most 2^31 - 1 segments");
+    hipStream_t s = (hipStream_t)stream;
+    int dev, cus;
+    xsum_status_t st = xsum::api_current_cus(&dev, &cus);
+    if (st != XSUM_OK)
+        return st;
+    // Work already queued on the stream may still produce the table or use
+    // this workspace: wait for it before reading the one or writing the other.
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return api_hip_fail(e, "hipStreamSynchronize");
+    std::vector<xsum_segment_t> table;
+    const xsum_segment_t *host_segs = segs;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, segs) == hipSuccess &&
+        attr.type == hipMemoryTypeDevice) {
+        table.resize(nseg);
+        e = hipMemcpy(table.data(), segs, nseg * sizeof(xsum_segment_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return api_hip_fail(e, "segment table download");
+        host_segs = table.data();
+    } else {
+        (void)hipGetLastError();   // a host pointer: the query may leave an error
+    }
+    HostPlan hp;
+    st = make_plan(host_segs, nseg, out_dtype, nullptr, cus, hp);
+    if (st != XSUM_OK)
+        return st;
+    const OneshotLayout L = oneshot_layout(nseg, hp.tasks.size(), hp.lanes.size(), hp.nslots);
+    if (ws_bytes < L.total)
+        return api_fail(XSUM_EINVAL, "workspace smaller than this table needs (" +
+                                         std::to_string(L.total) + " bytes)");
+    uint8_t *ws = (uint8_t *)workspace;
+    e = hipMemcpy(ws + L.segs, host_segs, nseg * sizeof(xsum::SegDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !hp.tasks.empty())
+        e = hipMemcpy(ws + L.tasks, hp.tasks.data(), hp.tasks.size() * sizeof(xsum::SegTask),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !hp.lanes.empty())
+        e = hipMemcpy(ws + L.lanes, hp.lanes.data(), hp.lanes.size() * sizeof(xsum::SegLane),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return api_hip_fail(e, "plan upload");
+    // control words and chunk states start at zero
+    e = xsum::launch_zero_words((uint64_t *)ws, L.segs / 8, s);
+    if (e == hipSuccess)
+        e = xsum::launch_segmented(base, (const xsum::SegDesc *)(ws + L.segs),
+                                   (const xsum::SegTask *)(ws + L.tasks),
+                                   (uint32_t)hp.tasks.size(), hp.small_from,
+                                   (const xsum::SegLane *)(ws + L.lanes),
+                                   (xsum_acc_t *)(ws + xsum::kSegCtlBytes), (xsum::SegCtl *)ws,
+                                   out_dtype, (uint64_t *)out, flags, hp.blocks, s);
+    return e == hipSuccess ? XSUM_OK : api_hip_fail(e, "kernel launch");
 }
 
 xsum_status_t xsum_segmented_run(const xsum_plan_t *plan, const void *base,
@@ -354,7 +485,7 @@ xsum_status_t xsum_segmented_run(const xsum_plan_t *plan, const void *base,
         (flags && (uintptr_t)flags % 4 != 0))
         return api_fail(XSUM_EINVAL, "misaligned out, flags or workspace");
     if (ws_bytes < plan->info.workspace_bytes)
-        return api_fail(XSUM_EINVAL, "workspace smaller than xsum_segmented_workspace_size()");
+        return api_fail(XSUM_EINVAL, "workspace smaller than xsum_plan_workspace_size()");
     int dev;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess)

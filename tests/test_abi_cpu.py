@@ -9,12 +9,13 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "xsum.h")
+HEADERS = [os.path.join(ROOT, "include", h)
+           for h in sorted(os.listdir(os.path.join(ROOT, "include"))) if h.endswith(".h")]
 LIB = os.path.join(ROOT, "paper_1605_05436_amd", "libxsum.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"\b(xsum_[a-z0-9_]+)\s*\(", text)
     return sorted(set(names))
@@ -186,3 +187,38 @@ int main(void) {
     dt = xs.batch_item_dtype()
     assert item == dt.itemsize and first == dt.fields["first_task"][1]
     assert isinstance(np.dtype(dt), np.dtype)
+
+
+def test_oneshot_segmented_rejects_bad_arguments_on_the_host(lib):
+    f = lib.xsum_exact_sum_segmented
+    f.restype = ctypes.c_int
+    vp = ctypes.c_void_p
+    f.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
+    # nothing to do
+    assert f(None, None, 0, 255, None, None, None, 0, None) == 0
+    # NULL table, base, out or workspace
+    assert f(4096, None, 3, 255, 4096, None, 4096, 1 << 20, None) == 1
+    assert f(None, 4096, 3, 255, 4096, None, 4096, 1 << 20, None) == 1
+    assert f(4096, 4096, 3, 255, None, None, 4096, 1 << 20, None) == 1
+    assert f(4096, 4096, 3, 255, 4096, None, None, 1 << 20, None) == 1
+    # base not 16-byte aligned, workspace not 256-byte aligned
+    assert f(4104, 4096, 3, 255, 4096, None, 4096, 1 << 20, None) == 1
+    assert f(4096, 4096, 3, 255, 4096, None, 4096 + 128, 1 << 20, None) == 1
+    assert "aligned" in _err(lib)
+    # too many segments
+    assert f(4096, 4096, 1 << 31, 255, 4096, None, 4096, 1 << 20, None) == 5
+
+
+def test_segmented_workspace_bound_grows_with_the_batch(lib):
+    f = lib.xsum_segmented_workspace_size
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    base = f(0, 0)
+    assert base >= 256 and base % 8 == 0
+    # per segment: a 24-byte descriptor, a 32-byte item, a 16-byte lane entry
+    assert f(1000, 0) >= base + 1000 * (24 + 32 + 16)
+    # a 2^30-element segment may be cut into 1 MiB chunks with one state
+    assert f(1, 1 << 30) >= f(1, 0) + 576 + 32 * ((1 << 30) >> 17)
+    for nseg, total in [(10, 100), (10**6, 2 * 10**9), (5, 1 << 40)]:
+        assert f(nseg, total) <= f(nseg + 1, total) <= f(nseg + 1, total + (1 << 20))
+    assert f(1 << 31, 0) == 0 and f(1, 1 << 51) == 0

@@ -239,3 +239,65 @@ def test_all_chunked_plan_replays():
     finally:
         xs.xsum_graph_destroy(g)
         ss.close()
+
+
+def _oneshot(dbuf, desc, segs_on_device, ws, ws_bytes, out_mode=None):
+    import torch
+    import paper_1605_05436_amd as xs
+    om = xs.SAME if out_mode is None else {"f64": 0, "f32": 1, "bf16": 2}[out_mode]
+    out = torch.full((max(1, len(desc)),), -1, dtype=torch.int64, device="cuda")
+    fl = torch.full((max(1, len(desc)),), -1, dtype=torch.int32, device="cuda")
+    table = np.ascontiguousarray(desc)
+    if segs_on_device:
+        dsegs = torch.from_numpy(table.view(np.uint8).copy()).to("cuda")
+        sp = dsegs.data_ptr()
+    else:
+        sp = table.ctypes.data
+    xs.xsum_exact_sum_segmented(dbuf.data_ptr(), sp, len(desc), om, out.data_ptr(),
+                                fl.data_ptr(), ws.data_ptr(), ws_bytes, xs.stream_handle())
+    torch.cuda.synchronize()
+    return (out.cpu().numpy().view(np.uint64)[:len(desc)],
+            fl.cpu().numpy().view(np.uint32)[:len(desc)])
+
+
+def test_oneshot_segmented_matches_oracle_in_a_bound_sized_workspace():
+    # one-shot call: table on the device and on the host, chunked segments
+    # included, twice in a row on one workspace (the second with a smaller
+    # table), every segment against the oracle
+    import torch
+    import paper_1605_05436_amd as xs
+    rng = np.random.default_rng(41)
+    lengths = np.concatenate([workloads.segment_lengths(3000, seed=41),
+                              [300_000, 700_001, 1, 0, 131_073]]).astype(np.int64)
+    dtypes = np.concatenate([workloads.segment_dtypes(3000, seed=42),
+                             [0, 0, 1, 2, 0]]).astype(np.int64)
+    buf, desc = workloads.config4(nseg=len(lengths), seed=43, lengths=lengths,
+                                  dtypes=dtypes)
+    dbuf = torch.from_numpy(buf).to("cuda")
+    total = int(desc["length"].sum())
+    ws_bytes = xs.xsum_segmented_workspace_size(len(desc), total)
+    ws = torch.empty(ws_bytes // 8 + 64, dtype=torch.int64, device="cuda")
+    ws.fill_(-1)              # the call zeroes what must start at zero
+    want = oracle.segmented_oracle_sums(buf, desc["byte_offset"], desc["length"],
+                                        desc["dtype"])
+    wb = np.array([w[0] for w in want], dtype=np.uint64)
+    wf = np.array([w[1] for w in want], dtype=np.uint32)
+    for on_dev in (True, False):
+        got = _oneshot(dbuf, desc, on_dev, ws, ws_bytes)
+        assert np.array_equal(got[0], wb) and np.array_equal(got[1], wf)
+    sub = desc[::3].copy()
+    got = _oneshot(dbuf, sub, True, ws, ws_bytes, out_mode="f32")
+    want32 = oracle.segmented_oracle_sums(buf, sub["byte_offset"], sub["length"],
+                                          sub["dtype"], out_fmt="f32")
+    assert [(int(b), int(f)) for b, f in zip(*got)] == want32
+
+
+def test_oneshot_segmented_rejects_a_small_workspace():
+    import torch
+    import paper_1605_05436_amd as xs
+    buf, desc = workloads.config4(nseg=200, seed=44)
+    dbuf = torch.from_numpy(buf).to("cuda")
+    ws = torch.zeros(64, dtype=torch.int64, device="cuda")
+    with pytest.raises(xs.XsumError) as e:
+        _oneshot(dbuf, desc, False, ws, 512)
+    assert e.value.status == xs.EINVAL and "workspace" in str(e.value)
