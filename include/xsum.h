@@ -331,6 +331,23 @@ xsum_status_t xsum_segmented_run(const xsum_plan_t *plan, const void *base,
                                  void *out, uint32_t *flags, void *workspace,
                                  size_t ws_bytes, void *stream);
 
+/*
+ * xsum_segmented_run for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid it): the
+ * workspace is a 1 MiB array that the library holds on each device until the
+ * process ends, so the caller passes only the plan, inputs and outputs.  The
+ * call allocates nothing; it clears the part of the array the plan uses with
+ * a fill kernel and launches the run, both on `stream`.
+ *   plan        its xsum_plan_workspace_size must be at most 1 MiB (control
+ *               words plus at most 1820 chunked segments), else XSUM_ERANGE
+ *   base, out, flags, stream as for xsum_segmented_run
+ * Every call on one device shares that device's array: calls that overlap
+ * (on different streams, or from different threads) race and give wrong
+ * results; order them.
+ */
+xsum_status_t xsum_segmented_run_noalloc(const xsum_plan_t *plan, const void *base,
+                                         void *out, uint32_t *flags, void *stream);
+
 /* Capture one xsum_segmented_run into an instantiated HIP graph (returned as
  * hipGraphExec_t in *graph_exec); replay it with xsum_graph_launch. */
 xsum_status_t xsum_segmented_capture(const xsum_plan_t *plan, const void *base,

@@ -34,7 +34,7 @@ EXPORTED = [
     "xsum_segmented_plan", "xsum_plan_destroy", "xsum_plan_get_info",
     "xsum_plan_workspace_size", "xsum_segmented_workspace_size",
     "xsum_exact_sum_segmented", "xsum_segmented_workspace_init",
-    "xsum_segmented_run", "xsum_segmented_capture", "xsum_graph_launch",
+    "xsum_segmented_run", "xsum_segmented_run_noalloc", "xsum_segmented_capture", "xsum_graph_launch",
     "xsum_graph_destroy", "xsum_batch_item_tasks", "xsum_batch_add",
     "xsum_batch_finalize", "xsum_probe_read", "xsum_probe_flush",
 ]
@@ -153,6 +153,8 @@ def _load():
     lib.xsum_segmented_workspace_init.argtypes = [vp, ctypes.c_size_t, vp]
     lib.xsum_segmented_run.restype = i32
     lib.xsum_segmented_run.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.xsum_segmented_run_noalloc.restype = i32
+    lib.xsum_segmented_run_noalloc.argtypes = [vp, vp, vp, vp, vp]
     lib.xsum_segmented_capture.restype = i32
     lib.xsum_segmented_capture.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t,
                                            ctypes.POINTER(vp)]
@@ -347,6 +349,11 @@ def xsum_segmented_workspace_init(ws, nbytes, stream=0):
 def xsum_segmented_run(plan, base, out, flags, ws, ws_bytes, stream=0):
     _check(_lib.xsum_segmented_run(_p(plan), _p(base), _p(out), _p(flags), _p(ws),
                                    ws_bytes, _p(stream)))
+
+
+def xsum_segmented_run_noalloc(plan, base, out, flags, stream=0):
+    _check(_lib.xsum_segmented_run_noalloc(_p(plan), _p(base), _p(out), _p(flags),
+                                           _p(stream)))
 
 
 def xsum_segmented_capture(plan, base, out, flags, ws, ws_bytes):

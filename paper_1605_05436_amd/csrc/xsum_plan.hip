@@ -33,6 +33,13 @@ hipError_t launch_batch_finalize(const uint32_t *slots, const uint32_t *fmts,
                                  uint32_t *flags, hipStream_t stream);
 }  // namespace xsum
 
+// Workspace of xsum_segmented_run_noalloc: one array per device, held until
+// the process ends.  Host code never uses this name as an address (on the
+// host it is only a stand-in for the symbol); it uses the device address
+// that hipGetSymbolAddress returns for the current device.
+static constexpr size_t kNoallocScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
 struct xsum_plan {
     int device = 0;
     uint64_t nseg = 0;
@@ -498,6 +505,49 @@ xsum_status_t xsum_segmented_run(const xsum_plan_t *plan, const void *base,
                                (xsum::SegCtl *)ws, plan->out_mode, (uint64_t *)out,
                                flags, plan->blocks, (hipStream_t)stream);
     return e == hipSuccess ? XSUM_OK : api_hip_fail(e, "kernel launch");
+}
+
+xsum_status_t xsum_segmented_run_noalloc(const xsum_plan_t *plan, const void *base,
+                                         void *out, uint32_t *flags, void *stream)
+{
+    // the scratch array's device address, looked up once per device
+    static std::mutex mu;
+    static std::vector<void *> addr;
+    if (plan == nullptr)
+        return api_fail(XSUM_EINVAL, "plan is NULL");
+    if (plan->info.workspace_bytes > kNoallocScratchBytes)
+        return api_fail(XSUM_ERANGE, "plan needs " + std::to_string(plan->info.workspace_bytes) +
+                                         " workspace bytes; the allocation-free run holds " +
+                                         std::to_string(kNoallocScratchBytes) +
+                                         " (at most 1820 chunked segments)");
+    if (plan->nseg == 0)
+        return XSUM_OK;
+    int dev;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return api_hip_fail(e, "hipGetDevice");
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if ((size_t)dev >= addr.size())
+            addr.resize((size_t)dev + 1, nullptr);
+        if (addr[dev] == nullptr) {
+            void *ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess)
+                return api_hip_fail(e, "hipGetSymbolAddress(scratch)");
+            addr[dev] = ptr;
+        }
+        ws = addr[dev];
+    }
+    // a previous call may have stopped before its end: the control words and
+    // chunk states this plan uses start at zero (a fill kernel, no memset, so
+    // the call may be captured)
+    e = xsum::launch_zero_words((uint64_t *)ws, (plan->info.workspace_bytes + 7) / 8,
+                                (hipStream_t)stream);
+    if (e != hipSuccess)
+        return api_hip_fail(e, "kernel launch");
+    return xsum_segmented_run(plan, base, out, flags, ws, kNoallocScratchBytes, stream);
 }
 
 xsum_status_t xsum_segmented_workspace_init(void *workspace, size_t ws_bytes,
