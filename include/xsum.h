@@ -263,7 +263,17 @@ typedef struct xsum_segment {
  *   two_lanes_from, four_lanes_from
  *                 segment sizes in bytes from which a segment summed in a lane
  *                 group gets two, then four lanes (default 2048 and 32768;
- *                 four_lanes_from below two_lanes_from is XSUM_ERANGE) */
+ *                 four_lanes_from below two_lanes_from is XSUM_ERANGE)
+ *   lanes[d][b]   per format d and size bucket b (lane-group segments of
+ *                 2^b to 2^(b+1) - 1 bytes; bucket 0 also holds empty ones,
+ *                 bucket 23 everything larger): the lanes each segment gets,
+ *                 1, 2, 4, 8 or 16 (0: as two_lanes_from / four_lanes_from
+ *                 decide; other values are XSUM_ERANGE)
+ *   lane_unroll[d][b]
+ *                 per format and size bucket: 16-byte vectors each lane has
+ *                 in flight per step, 8 or 16 (0: 16)
+ * Every tuning gives the same result bits; only the speed differs. */
+#define XSUM_TUNE_BUCKETS 24
 typedef struct xsum_seg_tuning {
     uint64_t lane_max[3];
     uint64_t wave_max[3];
@@ -272,6 +282,8 @@ typedef struct xsum_seg_tuning {
     uint32_t lane_buckets;
     uint64_t two_lanes_from;
     uint64_t four_lanes_from;
+    uint8_t lanes[3][XSUM_TUNE_BUCKETS];
+    uint8_t lane_unroll[3][XSUM_TUNE_BUCKETS];
 } xsum_seg_tuning_t;
 
 /* Plan statistics. */

@@ -23,6 +23,7 @@ OK, EINVAL, EDTYPE, ENOMEM, EHIP, ERANGE = 0, 1, 2, 3, 4, 5
 FLAG_INEXACT, FLAG_OVERFLOW, FLAG_NAN, FLAG_INF = 1, 2, 4, 8
 DIGITS = 68
 STATE_BYTES = 576
+TUNE_BUCKETS = 24
 OUT_BYTES = {F64: 8, F32: 4, BF16: 2}
 
 EXPORTED = [
@@ -51,7 +52,9 @@ class SegTuning(ctypes.Structure):
     _fields_ = [("lane_max", ctypes.c_uint64 * 3), ("wave_max", ctypes.c_uint64 * 3),
                 ("chunk_vectors", ctypes.c_uint64),
                 ("blocks_per_cu", ctypes.c_uint32), ("lane_buckets", ctypes.c_uint32),
-                ("two_lanes_from", ctypes.c_uint64), ("four_lanes_from", ctypes.c_uint64)]
+                ("two_lanes_from", ctypes.c_uint64), ("four_lanes_from", ctypes.c_uint64),
+                ("lanes", (ctypes.c_uint8 * TUNE_BUCKETS) * 3),
+                ("lane_unroll", (ctypes.c_uint8 * TUNE_BUCKETS) * 3)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -1,15 +1,25 @@
 """Autotuner for segmented sums and the single-sum grid.
 
 For a batch of segments the tunables decide which path each length bucket
-takes and how work is cut: lane_max (per-lane groups below it), wave_max (one
-wave per segment below it), chunk_vectors (chunk size above it),
-blocks_per_cu (resident one-wave groups per CU) and lane_buckets (length
-buckets per doubling inside the per-lane path).  The tuner times candidate
-plans on the device with captured-graph replays, checks that every candidate
-returns bit-identical results (exactness makes that a hard requirement, not a
-tolerance), and keeps the fastest.  Results are cached in a JSON file keyed
-by the device architecture and a coarse signature of the batch (per-format
-log2-length histogram), so later plans of similar batches reuse them.
+takes and how work is cut.  Global knobs: lane_max (per-lane groups below
+it), wave_max (one wave per segment below it), chunk_vectors (chunk size
+above it), blocks_per_cu (resident one-wave groups per CU) and lane_buckets
+(length buckets per doubling inside the per-lane path).  Per format and per
+log2-size bucket of the lane-group segments: the lanes each segment gets (1
+to 16) and the vectors each lane keeps in flight (8 or 16), which select
+different kernel code for that bucket's work items.
+
+The tuner first picks the global knobs by timing whole-batch candidate plans,
+then, bucket by bucket, times each lanes/unroll choice on a plan of that
+bucket's segments alone, and finally keeps the combined per-bucket table if
+the whole batch runs faster with it.  Every candidate's results must be bit
+identical to the first one's (exactness makes that a hard requirement, not a
+tolerance).  Timings start after a warm-up long enough for the device clock
+to settle, and candidates are timed in interleaved rounds (median per
+candidate), so slow phases of the clock hit all of them alike.  Results are
+cached in a JSON file keyed by the device architecture and a coarse
+signature of the batch (per-format log2-length histogram), so later plans of
+similar batches reuse them.
 
 The cache path is $XSUM_TUNE_CACHE, else ~/.cache/xsum/tune.json.
 """
@@ -21,8 +31,8 @@ import time
 
 import numpy as np
 
-from . import (SegTuning, SegmentedSum, xsum_graph_launch, xsum_graph_destroy,
-               stream_handle)
+from . import (SegTuning, SegmentedSum, TUNE_BUCKETS, xsum_graph_launch,
+               xsum_graph_destroy, stream_handle)
 
 DEFAULT_CANDIDATES = [
     # (lane_max per dtype, wave_max per dtype, chunk_vectors, blocks_per_cu,
@@ -69,13 +79,24 @@ def batch_signature(desc):
     return hashlib.sha1(key.encode()).hexdigest()[:16]
 
 
+NB = TUNE_BUCKETS
+EMPTY_TABLE = tuple(tuple(0 for _ in range(NB)) for _ in range(3))
+
+
 def _tuning(c):
+    """SegTuning from a candidate tuple (lane_max, wave_max, chunk_vectors,
+    blocks_per_cu, lane_buckets[, two_lanes_from, four_lanes_from[, lanes,
+    lane_unroll]]), the last two 3 x 24 tables."""
     lane, wave, chunk, bpc, buckets = c[:5]
     two, four = c[5:7] if len(c) >= 7 else (0, 0)
+    lanes, unroll = c[7:9] if len(c) >= 9 else (EMPTY_TABLE, EMPTY_TABLE)
     t = SegTuning()
     for d in range(3):
         t.lane_max[d] = lane[d]
         t.wave_max[d] = wave[d]
+        for b in range(NB):
+            t.lanes[d][b] = lanes[d][b]
+            t.lane_unroll[d][b] = unroll[d][b]
     t.chunk_vectors = chunk
     t.blocks_per_cu = bpc
     t.lane_buckets = buckets
@@ -84,46 +105,176 @@ def _tuning(c):
     return t
 
 
+def _full(c):
+    """The candidate with all nine fields."""
+    c = tuple(c)
+    if len(c) < 7:
+        c = c + (0, 0)
+    if len(c) < 9:
+        c = c + (EMPTY_TABLE, EMPTY_TABLE)
+    return c
+
+
 def _as_list(c):
-    return [list(c[0]), list(c[1])] + list(c[2:])
+    c = _full(c)
+    return [list(c[0]), list(c[1])] + list(c[2:7]) + \
+        [[list(r) for r in c[7]], [list(r) for r in c[8]]]
 
 
 def _from_list(c):
+    c = list(c)
+    if len(c) >= 9:
+        return (tuple(c[0]), tuple(c[1])) + tuple(c[2:7]) + \
+            (tuple(tuple(r) for r in c[7]), tuple(tuple(r) for r in c[8]))
     return (tuple(c[0]), tuple(c[1])) + tuple(c[2:])
 
 
-def _time_candidate(desc, dbuf, cand, reps, out, flags):
-    import torch
-    ss = SegmentedSum(desc, tuning=_tuning(cand))
-    g = ss.capture(dbuf, out, flags)
-    sh = stream_handle()
-    try:
-        for _ in range(2):
-            xsum_graph_launch(g, sh)
-        torch.cuda.synchronize()
+class _Graph:
+    """One candidate plan captured for a batch, with its own outputs."""
+
+    def __init__(self, desc, dbuf, cand):
+        import torch
+        self.ss = SegmentedSum(desc, tuning=_tuning(cand))
+        n = max(1, len(desc))
+        self.out = torch.zeros(n, dtype=torch.int64, device="cuda")
+        self.flags = torch.zeros(n, dtype=torch.int32, device="cuda")
+        self.g = self.ss.capture(dbuf, self.out, self.flags)
+
+    def time(self, reps):
+        import torch
+        sh = stream_handle()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        xsum_graph_launch(self.g, sh)
         e0.record()
         for _ in range(reps):
-            xsum_graph_launch(g, sh)
+            xsum_graph_launch(self.g, sh)
         e1.record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        res = (out.cpu().numpy().copy(), flags.cpu().numpy().copy())
-    finally:
-        xsum_graph_destroy(g)
-        ss.close()
-    return ms, res
+        return e0.elapsed_time(e1) / reps
+
+    def results(self):
+        return self.out.cpu().numpy().copy(), self.flags.cpu().numpy().copy()
+
+    def close(self):
+        xsum_graph_destroy(self.g)
+        self.ss.close()
 
 
-def tune_segmented(desc, dbuf, candidates=None, reps=5, use_cache=True,
-                   verbose=False, margin=0.03):
-    """Pick the fastest tuning for this batch.  Returns (tuning tuple, table)
-    where table lists (candidate, ms).  Raises if candidates disagree.  The
-    first candidate (the library defaults) is kept unless another is faster
-    by more than `margin` (relative), so near-ties between timings resolve
-    the same way from run to run."""
+def warm_up(graph, ms=150.0):
+    """Replay a graph for about `ms` milliseconds: the device clock drops
+    when a sustained load starts and takes tens of milliseconds to settle."""
     import torch
+    t0 = time.time()
+    while (time.time() - t0) * 1e3 < ms:
+        graph.time(4)
+    torch.cuda.synchronize()
+
+
+def _time_interleaved(desc, dbuf, cands, reps, rounds, verbose=False, tag=""):
+    """Capture every candidate, time them round-robin `rounds` times (reps
+    replays each), return [(cand, median ms)] and check that all results are
+    bit-identical to the first candidate's."""
+    graphs = [_Graph(desc, dbuf, c) for c in cands]
+    try:
+        warm_up(graphs[0])
+        times = [[] for _ in cands]
+        for _ in range(rounds):
+            for i, g in enumerate(graphs):
+                times[i].append(g.time(reps))
+        ref = graphs[0].results()
+        for c, g in zip(cands, graphs):
+            res = g.results()
+            if not (np.array_equal(res[0], ref[0]) and np.array_equal(res[1], ref[1])):
+                raise RuntimeError("autotune candidate %r changed the results" % (c,))
+    finally:
+        for g in graphs:
+            g.close()
+    table = [(c, float(np.median(t))) for c, t in zip(cands, times)]
+    if verbose:
+        for c, m in table:
+            print("[autotune]%s %r: %.4f ms" % (tag, c if len(str(c)) < 200 else "...", m),
+                  flush=True)
+    return table
+
+
+def _pick(table, margin):
+    """First entry unless another is faster by more than margin."""
+    best = table[0]
+    for c, m in table[1:]:
+        if m < best[1] * (1.0 - margin):
+            best = (c, m)
+    return best
+
+
+LANE_CHOICES = [(0, 0), (1, 16), (2, 16), (4, 16), (8, 16), (16, 16),
+                (1, 8), (2, 8), (4, 8), (8, 8), (16, 8)]
+
+
+def lane_buckets_of(desc, lane_max):
+    """(format, size bucket) -> indices of the segments that lane groups sum
+    (length <= lane_max of the format), bucket = floor(log2 bytes)."""
+    L = np.asarray(desc["length"], dtype=np.int64)
+    D = np.asarray(desc["dtype"], dtype=np.int64)
+    es = np.array([8, 4, 2], dtype=np.int64)[D]
+    lm = np.array(lane_max, dtype=np.int64)[D]
+    nb = L * es
+    b = np.where(nb > 0, np.floor(np.log2(np.maximum(nb, 1))), 0).astype(np.int64)
+    b = np.minimum(b, NB - 1)
+    groups = {}
+    sel = np.nonzero(L <= lm)[0]
+    for d in range(3):
+        for bb in range(NB):
+            idx = sel[(D[sel] == d) & (b[sel] == bb)]
+            if len(idx):
+                groups[(d, bb)] = idx
+    return groups
+
+
+def tune_buckets(desc, dbuf, base, reps=4, rounds=3, min_bytes=16 << 20,
+                 margin=0.03, verbose=False):
+    """Per (format, size bucket) of lane-group segments: the lanes per segment
+    and vectors in flight per lane that sum that bucket's segments fastest,
+    on a plan of those segments alone (other knobs as in `base`).  Buckets
+    holding fewer than min_bytes keep the defaults.  Returns (lanes table,
+    unroll table, per-bucket tables of timings)."""
+    from . import xsum_plan_get_info  # noqa: F401  (binding loaded)
+    base = _full(base)
+    lane_max = [v or dflt for v, dflt in zip(base[0], (16384, 16384, 32768))]
+    lanes = [[0] * NB for _ in range(3)]
+    unroll = [[0] * NB for _ in range(3)]
+    detail = {}
+    es = [8, 4, 2]
+    for (d, b), idx in sorted(lane_buckets_of(desc, lane_max).items()):
+        nbytes = int(np.asarray(desc["length"])[idx].sum()) * es[d]
+        if nbytes < min_bytes:
+            continue
+        sub = np.ascontiguousarray(desc[idx])
+        cands = []
+        for g, u in LANE_CHOICES:
+            tl = [list(r) for r in EMPTY_TABLE]
+            tu = [list(r) for r in EMPTY_TABLE]
+            tl[d][b], tu[d][b] = g, u
+            cands.append(base[:7] + (tuple(map(tuple, tl)), tuple(map(tuple, tu))))
+        table = _time_interleaved(sub, dbuf, cands, reps, rounds)
+        (best, _) = _pick(table, margin)
+        lanes[d][b] = best[7][d][b]
+        unroll[d][b] = best[8][d][b]
+        detail["%d/%d" % (d, b)] = [[c[7][d][b], c[8][d][b], round(m, 5)] for c, m in table]
+        if verbose:
+            print("[autotune] format %d bucket 2^%d (%d segments, %.1f MB): lanes %d unroll %d"
+                  % (d, b, len(idx), nbytes / 1e6, lanes[d][b], unroll[d][b]), flush=True)
+    return lanes, unroll, detail
+
+
+def tune_segmented(desc, dbuf, candidates=None, reps=4, rounds=3, use_cache=True,
+                   verbose=False, margin=0.03, per_bucket=True):
+    """Pick the fastest tuning for this batch.  Returns (tuning tuple, table)
+    where table lists (candidate, ms) of the global stage plus, with
+    per_bucket, the per-bucket table candidate.  Raises if candidates
+    disagree.  The first candidate (the library defaults) is kept unless
+    another is faster by more than `margin` (relative), so near-ties between
+    timings resolve the same way from run to run."""
     sig = batch_signature(desc)
     path = cache_path()
     cache = {}
@@ -134,25 +285,24 @@ def tune_segmented(desc, dbuf, candidates=None, reps=5, use_cache=True,
             cache = {}
         if sig in cache:
             return _from_list(cache[sig]["tuning"]), cache[sig]["table"]
-    cands = candidates or DEFAULT_CANDIDATES
-    out = torch.zeros(len(desc), dtype=torch.int64, device="cuda")
-    flags = torch.zeros(len(desc), dtype=torch.int32, device="cuda")
-    table, ref, best = [], None, None
-    for cand in cands:
-        ms, res = _time_candidate(desc, dbuf, cand, reps, out, flags)
-        if ref is None:
-            ref = res
-        elif not (np.array_equal(res[0], ref[0]) and np.array_equal(res[1], ref[1])):
-            raise RuntimeError("autotune candidate %r changed the results" % (cand,))
-        table.append((cand, ms))
-        if verbose:
-            print("[autotune] %r: %.3f ms" % (cand, ms), flush=True)
-        if best is None or ms < best[1] * (1.0 - margin):
-            best = (cand, ms)
+    cands = [_full(c) for c in (candidates or DEFAULT_CANDIDATES)]
+    table = _time_interleaved(desc, dbuf, cands, reps, rounds, verbose, " global")
+    best = _pick(table, margin)
+    detail = None
+    if per_bucket:
+        lanes, unroll, detail = tune_buckets(desc, dbuf, best[0], verbose=verbose,
+                                             margin=margin)
+        combined = best[0][:7] + (tuple(map(tuple, lanes)), tuple(map(tuple, unroll)))
+        if combined != best[0]:
+            t2 = _time_interleaved(desc, dbuf, [best[0], combined], reps, rounds,
+                                   verbose, " combined")
+            table = table + [t2[1]]
+            if t2[1][1] < t2[0][1] * (1.0 - margin):
+                best = t2[1]
     if use_cache:
         cache[sig] = {"tuning": _as_list(best[0]),
                       "table": [[_as_list(c), m] for c, m in table],
-                      "arch": _arch(), "time": time.time()}
+                      "buckets": detail, "arch": _arch(), "time": time.time()}
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             tmp = path + ".tmp%d" % os.getpid()

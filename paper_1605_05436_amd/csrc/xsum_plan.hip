@@ -136,6 +136,14 @@ xsum_status_t make_plan(const xsum_segment_t *segs, uint64_t nseg, int out_dtype
         }
         if (tuning->chunk_vectors)
             chunk_vectors = tuning->chunk_vectors;
+        for (int d = 0; d < 3; ++d)
+            for (int b = 0; b < XSUM_TUNE_BUCKETS; ++b) {
+                const uint8_t g = tuning->lanes[d][b], u = tuning->lane_unroll[d][b];
+                if (g > 16 || (g & (g - 1)) != 0)
+                    return api_fail(XSUM_ERANGE, "lanes per segment must be 1, 2, 4, 8 or 16");
+                if (u != 0 && u != 8 && u != 16)
+                    return api_fail(XSUM_ERANGE, "lane_unroll must be 8 or 16");
+            }
         blocks_per_cu = (int)tuning->blocks_per_cu;
         if (lane_max[0] > (1u << 20) || lane_max[1] > (1u << 22) || lane_max[2] > (1u << 23))
             return api_fail(XSUM_ERANGE, "lane_max too large");
@@ -244,10 +252,20 @@ xsum_status_t make_plan(const xsum_segment_t *segs, uint64_t nseg, int out_dtype
             // rounding is then shared by 64 segments), two or four for longer
             // ones, whose loads then touch fewer, longer runs of memory
             const uint64_t bytes0 = segs[ids[g]].length * kBytes[dt];
-            const uint32_t glog = bytes0 < two_lanes_from ? 0 : bytes0 < four_lanes_from ? 1 : 2;
+            uint32_t glog = bytes0 < two_lanes_from ? 0 : bytes0 < four_lanes_from ? 1 : 2;
+            uint32_t unroll8 = 0;
+            if (tuning) {
+                const int sb = bytes0 ? std::min(63 - __builtin_clzll(bytes0),
+                                                 XSUM_TUNE_BUCKETS - 1) : 0;
+                if (tuning->lanes[dt][sb])
+                    glog = (uint32_t)__builtin_ctz(tuning->lanes[dt][sb]);
+                if (tuning->lane_unroll[dt][sb] == 8)
+                    unroll8 = xsum::kLaneUnroll8;
+            }
             const size_t cnt = std::min<size_t>(64u >> glog, ids.size() - g);
             HostTask h{};
-            h.t.kind_dtype_flags = xsum::kLaneGroup | ((uint32_t)dt << 8) | (glog << 16);
+            h.t.kind_dtype_flags = xsum::kLaneGroup | ((uint32_t)dt << 8) |
+                                   ((glog | unroll8) << 16);
             h.t.a = (uint32_t)lanes.size();
             h.t.b = (uint32_t)cnt;
             uint64_t maxlen = 0;

@@ -26,8 +26,11 @@ enum SegChunkFlags : uint32_t {
     kChunkFirst = 1,  // also adds the segment's unaligned head elements
     kChunkLast = 2,   // also adds the segment's ragged tail elements
 };
-// A lane group's flags field is log2 of the lanes that share each segment
-// (0, 1 or 2: 64, 32 or 16 segments per group).
+// A lane group's flags field holds log2 of the lanes that share each
+// segment in its low three bits (0 to 4: 64 down to 4 segments per group)
+// and, in bit 3, whether each lane keeps 8 instead of 16 vectors in flight.
+static constexpr uint32_t kLaneGlogMask = 7u;
+static constexpr uint32_t kLaneUnroll8 = 8u;
 
 // 32-byte work item.
 struct SegTask {

@@ -73,26 +73,173 @@ __device__ __forceinline__ uint32_t wave_or_u32(uint32_t v)
     return v;
 }
 
-// Round the lane's own column and zero it.  binary64 columns are digits
-// 0..65.  A binned column holds 33 bins of weight 2^(8(b + kBin0)), each as a
-// positive and a negative entry; each bin's signed value is moved to its
-// radix-2^32 digit (kBin0 / 4 onwards), written back over the entries it came
-// from (digit kBin0 / 4 + i lands in entry i, never past an entry still to be
-// read), split into 32-bit halves so no shift overflows; two top digits take
-// any carry.
+// Two-pass rounding of one lane's digits held in rows [r0, r1) of its
+// column (row d at col[d * 64] is digit digit0 + d, weight
+// 2^(32 (digit0 + d)) in units of 2^-1074); every other row of the column is
+// zero.  Pass 1 carries the raw digits upward and writes the canonical
+// digits back, noting the lowest non-zero digit z, the highest non-zero
+// digit and the highest digit that is not all ones; the final carry is the
+// sign.  r1 must leave room above the highest row that received chunks for
+// the carries to settle (two rows).  Pass 2 reads the three digits the
+// rounding needs: for a negative sum the magnitude's digits are 0 below z,
+// 2^32 - u at z and 2^32 - 1 - u above it, so in both cases "any non-zero
+// digit below h - 2" is simply z < h - 2.  Rows [r0, r1) are zeroed
+// afterwards, so the whole column is zero again.
+__device__ __forceinline__ uint64_t finish_lane_window(uint64_t *col, int r0, int r1,
+                                                       int digit0, uint32_t special,
+                                                       int out_fmt, uint32_t &flags)
+{
+    int64_t carry = 0;
+    int z = -1, hnz = -1, hff = -1;
+    for (int d = r0; d < r1; ++d) {
+        const int64_t x = (int64_t)lds_load(col + d * 64) + carry;
+        const uint32_t u = (uint32_t)((uint64_t)x & kLow32);
+        carry = x >> 32;
+        lds_store(col + d * 64, u);
+        if (u != 0) {
+            hnz = d;
+            z = (z < 0) ? d : z;
+        }
+        if (u != 0xffffffffu)
+            hff = d;
+    }
+    const OutFormat f = out_format(out_fmt);
+    flags = 0;
+    uint64_t bits;
+    const bool negative = carry < 0;
+    if (special_result(special, f, bits, flags)) {
+    } else if (!(carry == 0 || carry == -1) || (negative && z < 0)) {
+        // beyond the digits: far above every format's range
+        flags = XSUM_FLAG_OVERFLOW | XSUM_FLAG_INEXACT;
+        bits = fmt_inf(f, negative);
+    } else if (!negative && hnz < 0) {
+        bits = 0;                                   // exact zero -> +0
+    } else {
+        const int h = negative ? (hff > z ? hff : z) : hnz;
+        uint32_t w[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int d = h - i;
+            uint32_t u = d >= 0 ? (uint32_t)lds_load(col + (d >= 0 ? d : 0) * 64) : 0u;
+            if (negative)
+                u = d < z ? 0u : (d == z ? 0u - u : ~u);
+            w[i] = u;
+        }
+        bits = round_magnitude(negative, digit0 + h, w[0], w[1], w[2], z < h - 2,
+                               f, flags);
+    }
+    for (int d = r0; d < r1; ++d)
+        lds_store(col + d * 64, 0);
+    return bits;
+}
+
+// Rows a lane's elements have touched, from the smallest and largest key it
+// met (Section 2: a sparse superaccumulator keeps only its active
+// components; a lane here keeps the bounds of its active rows).  Keys:
+// binary64 the exponent field e (rows of digits k and k + 1, k = (max(e,1) -
+// 1) >> 5); binned formats the magnitude bits a (the two entries of bin b).
+// kmin > kmax means no element.
 template <int FMT>
-__device__ __forceinline__ uint64_t finish_lane(uint64_t *col, uint32_t spec,
-                                                int out_fmt, uint32_t &flags)
+__device__ __forceinline__ uint32_t key_row_lo(uint32_t k)
+{
+    if constexpr (FMT == XSUM_F64)
+        return (max(k, 1u) - 1u) >> 5;
+    else if constexpr (FMT == XSUM_F32)
+        return 2 * ((max(k, 0x00800000u) + (4u << 23)) >> 26);
+    else
+        return 2 * ((max(k, 0x80u) + 0x200u) >> 10);
+}
+
+template <int FMT>
+__device__ __forceinline__ uint32_t key_row_hi(uint32_t k)
+{
+    return key_row_lo<FMT>(k) + 1;
+}
+
+// Running key bounds over the valid vectors of a step (vector j is valid for
+// j < nvalid; the others are the zero padding of lanes past their share).
+template <int FMT, int U>
+__device__ __forceinline__ void track_keys(const vec4u (&q)[U], uint64_t nvalid,
+                                           uint32_t &kmin, uint32_t &kmax)
+{
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const bool ok = (uint64_t)j < nvalid;
+        if constexpr (FMT == XSUM_F64) {
+            const uint32_t e0 = (q[j].y >> 20) & 0x7ffu, e1 = (q[j].w >> 20) & 0x7ffu;
+            kmin = min(kmin, ok ? min(e0, e1) : 0xffffffffu);
+            kmax = max(kmax, ok ? max(e0, e1) : 0u);
+        } else if constexpr (FMT == XSUM_F32) {
+            const uint32_t a0 = q[j].x & 0x7fffffffu, a1 = q[j].y & 0x7fffffffu,
+                           a2 = q[j].z & 0x7fffffffu, a3 = q[j].w & 0x7fffffffu;
+            kmin = min(kmin, ok ? min(min(a0, a1), min(a2, a3)) : 0xffffffffu);
+            kmax = max(kmax, ok ? max(max(a0, a1), max(a2, a3)) : 0u);
+        } else {
+            const vec4u m = q[j] & 0x7fff7fffu;
+            const uint32_t lo = min(min(m.x & 0xffffu, m.y & 0xffffu),
+                                    min(m.z & 0xffffu, m.w & 0xffffu));
+            const uint32_t hi = min(min(m.x >> 16, m.y >> 16), min(m.z >> 16, m.w >> 16));
+            const uint32_t mx = max(max(max(m.x & 0xffffu, m.y & 0xffffu),
+                                        max(m.z & 0xffffu, m.w & 0xffffu)),
+                                    max(max(m.x >> 16, m.y >> 16), max(m.z >> 16, m.w >> 16)));
+            kmin = min(kmin, ok ? min(lo, hi) : 0xffffffffu);
+            kmax = max(kmax, ok ? mx : 0u);
+        }
+    }
+}
+
+// The key of one element read with a scalar load.
+template <int FMT>
+__device__ __forceinline__ uint32_t scalar_key(const uint8_t *p)
+{
+    if constexpr (FMT == XSUM_F64)
+        return (((const uint32_t *)p)[1] >> 20) & 0x7ffu;
+    else if constexpr (FMT == XSUM_F32)
+        return *(const uint32_t *)p & 0x7fffffffu;
+    else
+        return (uint32_t)(*(const uint16_t *)p) & 0x7fffu;
+}
+
+// Carry step over rows [r0, r1) of a binary64 column: every row but the last
+// keeps its low 32 bits, its carry goes to the row above; the carries of row
+// r1 - 1 go to row r1.  The value is unchanged.
+__device__ __forceinline__ void normalise_rows(uint64_t *col, int r0, int r1)
+{
+    int64_t carry = 0;
+    for (int d = r0; d < r1; ++d) {
+        const int64_t x = (int64_t)lds_load(col + d * 64) + carry;
+        lds_store(col + d * 64, (uint64_t)x & kLow32);
+        carry = x >> 32;
+    }
+    lds_store(col + r1 * 64, lds_load(col + r1 * 64) + (uint64_t)carry);
+}
+
+// Round the lane's own column, whose rows outside [r0, r1) are zero, and
+// zero it.  binary64 columns are digits 0..65.  A binned column holds 33 bins
+// of weight 2^(8(b + kBin0)), each as a positive and a negative entry; each
+// bin's signed value is moved to its radix-2^32 digit (kBin0 / 4 onwards),
+// written back over the entries it came from (digit kBin0 / 4 + i lands in
+// entry i, never past an entry still to be read), split into 32-bit halves
+// so no shift overflows; two digits above the last take any carry.
+template <int FMT>
+__device__ __forceinline__ uint64_t finish_lane(uint64_t *col, int r0, int r1,
+                                                uint32_t spec, int out_fmt,
+                                                uint32_t &flags)
 {
     if constexpr (FMT == XSUM_F64) {
-        return finish_lane_digits<Geo<XSUM_F64>::kN>(col, 0, spec, out_fmt, flags);
+        // two rows above the highest that received chunks let carries settle
+        return finish_lane_window(col, r0, min(r1 + 2, Geo<XSUM_F64>::kN), 0, spec,
+                                  out_fmt, flags);
     } else {
         constexpr int kBin0 = Geo<FMT>::kBin0;
         constexpr int kDigit0 = kBin0 >> 2;
+        if (r0 >= r1)
+            return finish_lane_window(col, 0, 0, kDigit0, spec, out_fmt, flags);
+        const int b0 = r0 >> 1, b1 = (r1 - 1) >> 1;   // bins b0..b1
+        const int g0 = (b0 + kBin0) >> 2;
         int64_t cur = 0, nxt = 0;                  // digits g and g + 1
-        int g_prev = kDigit0;
-#pragma unroll
-        for (int b = 0; b < Geo<FMT>::kBins; ++b) {
+        int g_prev = g0;
+        for (int b = b0; b <= b1; ++b) {
             const int g = (b + kBin0) >> 2;
             const int sh = 8 * ((b + kBin0) & 3);
             const int64_t v = (int64_t)lds_load(col + (2 * b) * 64) -
@@ -109,33 +256,33 @@ __device__ __forceinline__ uint64_t finish_lane(uint64_t *col, uint32_t spec,
             nxt += (int64_t)(lo >> 32) + hi;
         }
         // the last two digits, then two empty digits for the carry
-        constexpr int kLast = (Geo<FMT>::kBins - 1 + kBin0) >> 2;
-        lds_store(col + (kLast - kDigit0) * 64, (uint64_t)cur);
-        lds_store(col + (kLast + 1 - kDigit0) * 64, (uint64_t)nxt);
-        lds_store(col + (kLast + 2 - kDigit0) * 64, 0);
-        lds_store(col + (kLast + 3 - kDigit0) * 64, 0);
-        const uint64_t bits = finish_lane_digits<kLast + 4 - kDigit0>(col, kDigit0, spec,
-                                                                      out_fmt, flags);
-        // entries above the digits were left as they were
-#pragma unroll
-        for (int b = kLast + 4 - kDigit0; b < Geo<FMT>::kN; ++b)
-            lds_store(col + b * 64, 0);
+        const int e1 = g_prev - kDigit0;
+        lds_store(col + e1 * 64, (uint64_t)cur);
+        lds_store(col + (e1 + 1) * 64, (uint64_t)nxt);
+        lds_store(col + (e1 + 2) * 64, 0);
+        lds_store(col + (e1 + 3) * 64, 0);
+        const uint64_t bits = finish_lane_window(col, g0 - kDigit0, e1 + 4, kDigit0, spec,
+                                                 out_fmt, flags);
+        // bin entries above the digits were left as they were
+        for (int d = e1 + 4; d < r1; ++d)
+            lds_store(col + d * 64, 0);
         return bits;
     }
 }
 
-// Add the entries of the NL - 1 columns to the right of this lane's into its
-// own.  Every read is independent, so the rows are unrolled and the reads
-// issued in batches.
-template <int N, int NL>
-__device__ __forceinline__ void fold_columns(uint64_t *col)
+// Add the rows [r0, r1) of the NL - 1 columns to the right of this lane's
+// into its own.  Every read of a row is independent, so the reads of a row
+// are issued together.
+template <int NL>
+__device__ __forceinline__ void fold_columns(uint64_t *col, int r0, int r1)
 {
-#pragma unroll
-    for (int d = 0; d < N; ++d) {
+    for (int d = r0; d < r1; ++d) {
         int64_t v = (int64_t)lds_load(col + d * 64);
 #pragma unroll
-        for (int k = 1; k < NL; ++k)
+        for (int k = 1; k < NL; ++k) {
             v += (int64_t)lds_load(col + d * 64 + k);
+            lds_store(col + d * 64 + k, 0);
+        }
         lds_store(col + d * 64, (uint64_t)v);
     }
 }
@@ -144,8 +291,11 @@ __device__ __forceinline__ void fold_columns(uint64_t *col)
 // first `count` valid).  Lane l reads every 2^glog-th 16-byte vector of
 // segment l >> glog, starting at vector l mod 2^glog, into its own column, so
 // a load instruction touches 64 >> glog runs of 2^glog contiguous vectors
-// instead of 64 scattered ones.  The columns of a segment's lanes are then
-// carry-normalised, summed into its first lane's column, and rounded there.
+// instead of 64 scattered ones.  Each lane keeps the bounds of the rows its
+// elements touched, and every later step (carry steps, the fold of a
+// segment's columns into its first lane's, the rounding and the clearing)
+// works on those rows only: short segments of data with a narrow exponent
+// range touch a few of the 66 rows.
 template <int FMT, int UL>
 __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLane &e,
                                                uint32_t count, uint32_t glog,
@@ -169,10 +319,11 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
     // this lane's vectors: sub, sub + 2^glog, ...
     const uint64_t my_nv = nv > sub ? ((nv - sub - 1) >> glog) + 1 : 0;
     uint32_t spec = 0;
+    uint32_t kmin = 0xffffffffu, kmax = 0;
 
     const uint64_t my_iters = (my_nv + UL - 1) / UL;
     const uint32_t iters = wave_max_u32((uint32_t)my_iters);
-    // binary64: at most 1024 + 2*UL + 2 elements between normalisations
+    // binary64: at most 1024 + 2*UL + 2 elements between carry steps
     constexpr int kNormIters = 512 / UL;
     int since = 0;
     // each lane walks its share of its segment, UL vectors per step, the next
@@ -181,7 +332,7 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
     // Every lane loads on every step (no load sits in a branch, so the
     // compiler's wait counts keep the spare buffer's loads in flight): a
     // lane past the end of its share, or a step past the last, loads the
-    // zero vector instead.
+    // zero vector instead (and leaves it out of its row bounds).
     auto load_step = [&](vec4u (&q)[UL], uint32_t it) {
 #pragma unroll
         for (int j = 0; j < UL; ++j) {
@@ -190,10 +341,16 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
             q[j] = *src;    // cached: neighbouring loads share lines
         }
     };
-    auto norm_step = [&]() {
+    auto add_step = [&](const vec4u (&q)[UL], uint32_t it) {
+        const uint64_t done = (uint64_t)it * UL;
+        track_keys<FMT, UL>(q, my_nv > done ? my_nv - done : 0, kmin, kmax);
+        add_tile<FMT, UL>(q, col, spec);
         if constexpr (FMT == XSUM_F64) {
             if (++since >= kNormIters) {
-                normalise_column<G::kN>(col);
+                // rows below the lowest and above the highest touched one
+                // (plus the carry row) are zero
+                normalise_rows(col, (int)key_row_lo<FMT>(kmin),
+                               min((int)key_row_hi<FMT>(kmax) + 1, G::kN - 1));
                 since = 0;
             }
         }
@@ -204,46 +361,78 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
         load_step(qa, 0);
     for (uint32_t it = 0; it < iters; it += 2) {
         load_step(qb, it + 1);
-        add_tile<FMT, UL>(qa, col, spec);
-        norm_step();
+        add_step(qa, it);
         if (it + 1 >= iters)
             break;
         load_step(qa, it + 2);
-        add_tile<FMT, UL>(qb, col, spec);
-        norm_step();
+        add_step(qb, it + 1);
     }
     if (sub == 0) {
-        for (uint64_t i = 0; i < head; ++i)
+        for (uint64_t i = 0; i < head; ++i) {
+            const uint32_t k = scalar_key<FMT>(p + i * G::kBytes);
+            kmin = min(kmin, k);
+            kmax = max(kmax, k);
             add_scalar<FMT>(p + i * G::kBytes, col, spec);
+        }
         const uint8_t *tp = p + head * G::kBytes + nv * 16;
-        for (uint64_t i = 0; i < tail; ++i)
+        for (uint64_t i = 0; i < tail; ++i) {
+            const uint32_t k = scalar_key<FMT>(tp + i * G::kBytes);
+            kmin = min(kmin, k);
+            kmax = max(kmax, k);
             add_scalar<FMT>(tp + i * G::kBytes, col, spec);
+        }
+    }
+    // the rows this lane may have written: binary64 also the carry row above
+    // the highest touched one
+    int r0 = G::kN, r1 = 0;
+    if (kmin <= kmax) {
+        r0 = (int)key_row_lo<FMT>(kmin);
+        r1 = (int)key_row_hi<FMT>(kmax) + 1;
+        if constexpr (FMT == XSUM_F64)
+            r1 = min(r1 + 1, G::kN);
     }
     if (glog > 0) {
         // the segment's lanes are neighbours: fold their columns into the
-        // first one.  Binary64 columns are carry-normalised first (entries
-        // below 2^32, the last one holding only carries), so a sum of up to
-        // four entries cannot overflow; binary32 bins hold at most lane_max
+        // first one.  Binary64 columns get a carry step first (entries below
+        // 2^32, the row above holding only carries), so a sum of up to 16
+        // entries cannot overflow; binary32 bins hold at most lane_max
         // chunks below 2^31 each.
         for (uint32_t k = 1; k < (1u << glog); k <<= 1)
             spec |= (uint32_t)__shfl_xor((int)spec, (int)k, 64);
-        if constexpr (FMT == XSUM_F64)
-            normalise_column<G::kN>(col);
+        if constexpr (FMT == XSUM_F64) {
+            if (r0 < r1) {
+                const int top = min(r1, G::kN - 1);
+                normalise_rows(col, r0, top);
+                r1 = top + 1;
+            }
+        }
+        for (uint32_t k = 1; k < (1u << glog); k <<= 1) {
+            r0 = min(r0, __shfl_xor(r0, (int)k, 64));
+            r1 = max(r1, __shfl_xor(r1, (int)k, 64));
+        }
         wave_lds_fence();
         if (sub == 0) {
             if (glog == 1)
-                fold_columns<G::kN, 2>(col);
+                fold_columns<2>(col, r0, r1);
+            else if (glog == 2)
+                fold_columns<4>(col, r0, r1);
+            else if (glog == 3)
+                fold_columns<8>(col, r0, r1);
             else
-                fold_columns<G::kN, 4>(col);
+                fold_columns<16>(col, r0, r1);
         }
         wave_lds_fence();
+        if (sub != 0) {         // folded into the first lane and cleared
+            r0 = G::kN;
+            r1 = 0;
+        }
     }
 
     const int of = out_mode == XSUM_SAME ? LaneOut<FMT>::kNatural : out_mode;
     uint32_t fl;
-    // every lane rounds (and clears) its own column; only a segment's first
+    // every lane rounds (and clears) its own rows; only a segment's first
     // lane holds the whole sum and writes it
-    const uint64_t bits = finish_lane<FMT>(col, spec, of, fl);
+    const uint64_t bits = finish_lane<FMT>(col, r0, r1, spec, of, fl);
     if (live && sub == 0) {
         out[s] = bits;
         if (flags)
@@ -444,7 +633,7 @@ __device__ __forceinline__ SegLane lane_entry(const SegLane *__restrict__ lanes,
                                               int lane)
 {
     SegLane e{0, 0, 0};
-    const uint32_t seg = (uint32_t)lane >> (t.kind_dtype_flags >> 16);
+    const uint32_t seg = (uint32_t)lane >> ((t.kind_dtype_flags >> 16) & kLaneGlogMask);
     if (ntasks_left && (t.kind_dtype_flags & 0xffu) == kLaneGroup && seg < t.b)
         e = lanes[t.a + seg];
     return e;
@@ -515,16 +704,29 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
         const uint32_t kind = t.kind_dtype_flags & 0xffu;
         const uint32_t dtype = (t.kind_dtype_flags >> 8) & 0xffu;
         if (kind == kLaneGroup) {
-            const uint32_t glog = t.kind_dtype_flags >> 16;
-            if (dtype == XSUM_F64)
-                run_lane_group<XSUM_F64, UL>(base, e, t.b, glog, col, out_mode, out, flags,
-                                              (const vec4u *)ctl->zero, lane);
-            else if (dtype == XSUM_F32)
-                run_lane_group<XSUM_F32, UL>(base, e, t.b, glog, col, out_mode, out, flags,
-                                              (const vec4u *)ctl->zero, lane);
-            else
-                run_lane_group<XSUM_BF16, UL>(base, e, t.b, glog, col, out_mode, out, flags,
-                                              (const vec4u *)ctl->zero, lane);
+            const uint32_t glog = (t.kind_dtype_flags >> 16) & kLaneGlogMask;
+            const vec4u *zero = (const vec4u *)ctl->zero;
+            if ((t.kind_dtype_flags >> 16) & kLaneUnroll8) {
+                if (dtype == XSUM_F64)
+                    run_lane_group<XSUM_F64, UL / 2>(base, e, t.b, glog, col, out_mode, out,
+                                                      flags, zero, lane);
+                else if (dtype == XSUM_F32)
+                    run_lane_group<XSUM_F32, UL / 2>(base, e, t.b, glog, col, out_mode, out,
+                                                      flags, zero, lane);
+                else
+                    run_lane_group<XSUM_BF16, UL / 2>(base, e, t.b, glog, col, out_mode, out,
+                                                       flags, zero, lane);
+            } else {
+                if (dtype == XSUM_F64)
+                    run_lane_group<XSUM_F64, UL>(base, e, t.b, glog, col, out_mode, out, flags,
+                                                  zero, lane);
+                else if (dtype == XSUM_F32)
+                    run_lane_group<XSUM_F32, UL>(base, e, t.b, glog, col, out_mode, out, flags,
+                                                  zero, lane);
+                else
+                    run_lane_group<XSUM_BF16, UL>(base, e, t.b, glog, col, out_mode, out, flags,
+                                                   zero, lane);
+            }
         } else if (kind == kWhole) {
             if (dtype == XSUM_F64)
                 run_whole<XSUM_F64, UC>(base, t, w, col, out_mode, out, flags, lane);

@@ -26,17 +26,10 @@ def _lib():
 
 def expected(buf, desc, out_fmt=None):
     """Oracle (bits, flags) per segment."""
-    res = np.zeros(len(desc), dtype=np.uint64)
-    fl = np.zeros(len(desc), dtype=np.uint32)
-    for i, (off, length, dt, _) in enumerate(desc.tolist()):
-        seg = buf[off:off + length * SIZE[dt]].view(UINT[dt])
-        of = out_fmt if out_fmt else ("f64" if dt == 0 else "f32")
-        if length > 50_000:
-            b, f = oracle.oracle_sum_binned(seg, NAMES[dt], of, threads=4)
-        else:
-            b, f = oracle.oracle_sum(seg, NAMES[dt], of)
-        res[i], fl[i] = b, f
-    return res, fl
+    want = oracle.segmented_oracle_sums(buf, desc["byte_offset"], desc["length"],
+                                        desc["dtype"], out_fmt=out_fmt)
+    return (np.array([w[0] for w in want], dtype=np.uint64),
+            np.array([w[1] for w in want], dtype=np.uint32))
 
 
 def run_gpu(buf, desc, out_mode=None, tuning=None, repeats=1):
@@ -165,8 +158,12 @@ def test_autotuner_picks_a_candidate_with_identical_results(tmp_path, monkeypatc
     buf, desc = workloads.config4(nseg=4000, seed=11)
     dbuf = torch.from_numpy(buf).to("cuda")
     cands = autotune.DEFAULT_CANDIDATES[:4]
-    best, table = autotune.tune_segmented(desc, dbuf, candidates=cands, reps=2)
-    assert best in cands and len(table) == len(cands)
+    best, table = autotune.tune_segmented(desc, dbuf, candidates=cands, reps=2,
+                                          per_bucket=True)
+    # the global knobs come from one candidate; the per-bucket tables are the
+    # tuner's own (the whole-batch comparison adds one table entry)
+    assert best[:7] in [autotune._full(c)[:7] for c in cands]
+    assert len(cands) <= len(table) <= len(cands) + 1
     # cached: the second call returns the same choice without timing
     best2, _ = autotune.tune_segmented(desc, dbuf, candidates=cands, reps=2)
     assert best2 == best
@@ -301,3 +298,70 @@ def test_oneshot_segmented_rejects_a_small_workspace():
     with pytest.raises(xs.XsumError) as e:
         _oneshot(dbuf, desc, False, ws, 512)
     assert e.value.status == xs.EINVAL and "workspace" in str(e.value)
+
+
+def _tuned(lanes, unroll):
+    import paper_1605_05436_amd as xs
+    t = xs.SegTuning()
+    for d in range(3):
+        for b in range(xs.TUNE_BUCKETS):
+            t.lanes[d][b] = lanes
+            t.lane_unroll[d][b] = unroll
+    return t
+
+
+@pytest.mark.parametrize("kmin,kmax", [(-50, 50), (-1000, 1000)])
+@pytest.mark.parametrize("lanes,unroll", [(1, 16), (2, 8), (4, 16), (8, 16), (8, 8),
+                                          (16, 16), (16, 8)])
+def test_lanes_per_segment_and_unroll_keep_the_bits(lanes, unroll, kmin, kmax):
+    """Every lanes-per-segment and vectors-in-flight choice, on a narrow and
+    a full-width exponent range (few or many active rows per lane)."""
+    buf, desc = workloads.config4(nseg=2500, seed=21, kmin=kmin, kmax=kmax)
+    check(buf, desc, tuning=_tuned(lanes, unroll))
+
+
+def _patterned_segments(rng):
+    """Segments whose active rows sit at the edges of the column: subnormals
+    only (rows 0-1), +-DBL_MAX (the top rows), zeros mixed with one value,
+    signed zeros, a special value, one tiny and one huge value together,
+    and binary32 / bfloat16 at both ends of their ranges."""
+    f64 = []
+    sub = rng.integers(1, 1 << 52, size=700, dtype=np.uint64)
+    sub |= rng.integers(0, 2, size=700, dtype=np.uint64) << np.uint64(63)
+    f64.append(sub)
+    big = np.full(301, 0x7FEFFFFFFFFFFFFF, dtype=np.uint64)
+    big[::2] |= np.uint64(1 << 63)
+    f64.append(big)
+    z = np.zeros(999, dtype=np.uint64)
+    z[500] = 0x3FF0000000000001
+    f64.append(z)
+    f64.append(np.full(64, 1 << 63, dtype=np.uint64))          # -0.0
+    sp = workloads.config1(900, seed=7)
+    sp[450] = 0x7FF0000000000000
+    f64.append(sp)
+    two = np.zeros(5000, dtype=np.uint64)
+    two[0], two[4999] = 1, 0x7FE0000000000000
+    f64.append(two)
+    f32 = [np.full(333, 0x7F7FFFFF, dtype=np.uint32), np.arange(1, 800, dtype=np.uint32),
+           np.zeros(257, dtype=np.uint32)]
+    bf = [np.full(2049, 0x7F7F, dtype=np.uint16), np.arange(1, 3000, dtype=np.uint16) & 0x807F]
+    return [(0, a) for a in f64] + [(1, a) for a in f32] + [(2, a) for a in bf]
+
+
+@pytest.mark.parametrize("lanes", [0, 1, 4, 16])
+def test_window_edges(lanes):
+    rng = np.random.default_rng(22)
+    specs = _patterned_segments(rng)
+    chunks, rows, at = [], [], 0
+    for d, a in specs:
+        raw = a.view(np.uint8)
+        rows.append((at, len(a), d, 0))
+        chunks.append(raw)
+        pad = (-raw.size) % 16
+        chunks.append(np.zeros(pad, dtype=np.uint8))
+        at += raw.size + pad
+    buf = np.concatenate(chunks)
+    desc = np.array(rows, dtype=workloads.SEGMENT_DTYPE)
+    t = _tuned(lanes, 16) if lanes else None
+    check(buf, desc, tuning=t)
+    check(buf, desc, out_mode="f32", tuning=t)
