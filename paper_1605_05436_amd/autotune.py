@@ -207,8 +207,13 @@ def _pick(table, margin):
     return best
 
 
-LANE_CHOICES = [(0, 0), (1, 16), (2, 16), (4, 16), (8, 16), (16, 16),
-                (1, 8), (2, 8), (4, 8), (8, 8), (16, 8)]
+LANE_CHOICES = (1, 2, 4, 8, 16)
+
+
+def default_lanes(nbytes, two_from=2048, four_from=32768):
+    """Lanes per segment the planner gives a lane-group segment of nbytes
+    bytes when the tuning table leaves its bucket at 0."""
+    return 1 if nbytes < two_from else 2 if nbytes < four_from else 4
 
 
 def lane_buckets_of(desc, lane_max):
@@ -231,39 +236,55 @@ def lane_buckets_of(desc, lane_max):
     return groups
 
 
-def tune_buckets(desc, dbuf, base, reps=4, rounds=3, min_bytes=16 << 20,
-                 margin=0.03, verbose=False):
-    """Per (format, size bucket) of lane-group segments: the lanes per segment
-    and vectors in flight per lane that sum that bucket's segments fastest,
-    on a plan of those segments alone (other knobs as in `base`).  Buckets
-    holding fewer than min_bytes keep the defaults.  Returns (lanes table,
-    unroll table, per-bucket tables of timings)."""
-    from . import xsum_plan_get_info  # noqa: F401  (binding loaded)
+def tune_buckets(desc, dbuf, base, reps=6, rounds=3, min_frac=0.01, margin=0.01,
+                 verbose=False):
+    """Lanes per segment for each (format, size bucket) of lane-group
+    segments, chosen in the context of the batch: buckets are visited
+    largest first, and each one's choices are timed on the whole share of
+    its format (the other buckets as chosen so far), since a bucket timed
+    alone is dominated by the launch's fixed costs.  Buckets holding less
+    than min_frac of their format's bytes keep the planner's choice.
+    Returns (lanes table, unroll table, per-bucket timings)."""
     base = _full(base)
     lane_max = [v or dflt for v, dflt in zip(base[0], (16384, 16384, 32768))]
-    lanes = [[0] * NB for _ in range(3)]
-    unroll = [[0] * NB for _ in range(3)]
-    detail = {}
+    two = base[5] or 2048
+    four = base[6] or 32768
     es = [8, 4, 2]
-    for (d, b), idx in sorted(lane_buckets_of(desc, lane_max).items()):
-        nbytes = int(np.asarray(desc["length"])[idx].sum()) * es[d]
-        if nbytes < min_bytes:
+    L = np.asarray(desc["length"], dtype=np.int64)
+    D = np.asarray(desc["dtype"], dtype=np.int64)
+    lanes = [[0] * NB for _ in range(3)]
+    unroll = [list(r) for r in base[8]]
+    for d in range(3):
+        for b in range(NB):
+            lanes[d][b] = base[7][d][b] or default_lanes(1 << b, two, four)
+    detail = {}
+    groups = lane_buckets_of(desc, lane_max)
+    for d in range(3):
+        share = np.ascontiguousarray(desc[D == d])
+        total = int(L[D == d].sum()) * es[d]
+        if len(share) == 0 or total == 0:
             continue
-        sub = np.ascontiguousarray(desc[idx])
-        cands = []
-        for g, u in LANE_CHOICES:
-            tl = [list(r) for r in EMPTY_TABLE]
-            tu = [list(r) for r in EMPTY_TABLE]
-            tl[d][b], tu[d][b] = g, u
-            cands.append(base[:7] + (tuple(map(tuple, tl)), tuple(map(tuple, tu))))
-        table = _time_interleaved(sub, dbuf, cands, reps, rounds)
-        (best, _) = _pick(table, margin)
-        lanes[d][b] = best[7][d][b]
-        unroll[d][b] = best[8][d][b]
-        detail["%d/%d" % (d, b)] = [[c[7][d][b], c[8][d][b], round(m, 5)] for c, m in table]
-        if verbose:
-            print("[autotune] format %d bucket 2^%d (%d segments, %.1f MB): lanes %d unroll %d"
-                  % (d, b, len(idx), nbytes / 1e6, lanes[d][b], unroll[d][b]), flush=True)
+        order = sorted(((int(L[idx].sum()) * es[d], b) for (dd, b), idx in groups.items()
+                        if dd == d), reverse=True)
+        for nbytes, b in order:
+            if nbytes < min_frac * total:
+                continue
+            cur = lanes[d][b]
+            choices = [cur] + [g for g in LANE_CHOICES if g != cur]
+            cands = []
+            for g in choices:
+                tl = [list(r) for r in lanes]
+                tl[d][b] = g
+                cands.append(base[:7] + (tuple(map(tuple, tl)), tuple(map(tuple, unroll))))
+            table = _time_interleaved(share, dbuf, cands, reps, rounds)
+            best = _pick(table, margin)[0]
+            lanes[d][b] = best[7][d][b]
+            detail["%d/%d" % (d, b)] = [[g, round(m, 5)] for g, (_, m) in zip(choices, table)]
+            if verbose:
+                print("[autotune] format %d bucket 2^%d (%.1f MB): %s -> %d lanes"
+                      % (d, b, nbytes / 1e6, " ".join("%d:%.4f" % (g, m) for g, (_, m)
+                                                      in zip(choices, table)),
+                         lanes[d][b]), flush=True)
     return lanes, unroll, detail
 
 
@@ -290,8 +311,7 @@ def tune_segmented(desc, dbuf, candidates=None, reps=4, rounds=3, use_cache=True
     best = _pick(table, margin)
     detail = None
     if per_bucket:
-        lanes, unroll, detail = tune_buckets(desc, dbuf, best[0], verbose=verbose,
-                                             margin=margin)
+        lanes, unroll, detail = tune_buckets(desc, dbuf, best[0], verbose=verbose)
         combined = best[0][:7] + (tuple(map(tuple, lanes)), tuple(map(tuple, unroll)))
         if combined != best[0]:
             t2 = _time_interleaved(desc, dbuf, [best[0], combined], reps, rounds,

@@ -287,6 +287,76 @@ __device__ __forceinline__ void fold_columns(uint64_t *col, int r0, int r1)
     }
 }
 
+// A lane's share of its segment in a lane group of 2^glog lanes per
+// segment: every 2^glog-th 16-byte vector, starting at vector sub.
+struct LaneShare {
+    const uint8_t *p;       // the segment's first element
+    const vec4u *vp;        // this lane's first vector
+    uint64_t head, nv, tail, my_nv;
+    uint32_t sub;
+    bool live;
+};
+
+// ebytes_log2: log2 of the element size (3, 2 or 1).
+__device__ __forceinline__ LaneShare lane_share(const uint8_t *base, const SegLane &e,
+                                                uint32_t count, uint32_t glog,
+                                                uint32_t ebytes_log2, int lane)
+{
+    LaneShare s;
+    s.sub = (uint32_t)lane & ((1u << glog) - 1);
+    s.live = ((uint32_t)lane >> glog) < count;
+    const uint64_t off = s.live ? e.byte_offset : 0;
+    const uint64_t L = s.live ? e.length : 0;
+    s.p = base + off;
+    s.head = (((16 - ((uintptr_t)s.p & 15)) & 15) >> ebytes_log2);
+    if (s.head > L)
+        s.head = L;
+    s.nv = (L - s.head) >> (4 - ebytes_log2);
+    s.tail = L - s.head - (s.nv << (4 - ebytes_log2));
+    s.vp = (const vec4u *)(s.p + (s.head << ebytes_log2)) + s.sub;
+    s.my_nv = s.nv > s.sub ? ((s.nv - s.sub - 1) >> glog) + 1 : 0;
+    return s;
+}
+
+// Step `it` of a lane's share: its vectors it*UL .. it*UL + UL - 1 (zero
+// vectors past the end).  Every lane loads on every step (no load sits in a
+// branch, so the compiler's wait counts keep a spare buffer's loads in
+// flight).  In a step where every lane's share is either whole or over, a
+// lane's loads walk one pointer by a fixed stride (zero for a lane that
+// reads the zero vector); only a step that ends some lane's share inside it
+// picks an address per vector.
+__device__ __forceinline__ bool whole_step(uint64_t my_nv, uint32_t it, int ul)
+{
+    const int64_t rem = (int64_t)my_nv - (int64_t)it * ul;
+    return __ballot(rem > 0 && rem < ul) == 0;
+}
+
+template <int UL, int CAP>
+__device__ __forceinline__ void load_lane_step(vec4u (&q)[CAP], const vec4u *vp,
+                                               uint64_t my_nv, uint32_t it, uint32_t glog,
+                                               const vec4u *zero)
+{
+    static_assert(UL <= CAP, "buffer too small");
+    const int64_t rem = (int64_t)my_nv - (int64_t)it * UL;
+    if (whole_step(my_nv, it, UL)) {
+        const uint8_t *a = rem > 0 ? (const uint8_t *)(vp + ((uint64_t)it * UL << glog))
+                                   : (const uint8_t *)zero;
+        const uint64_t st = rem > 0 ? (16ull << glog) : 0;
+#pragma unroll
+        for (int j = 0; j < UL; ++j) {
+            q[j] = *(const vec4u *)a;   // cached: neighbouring loads share lines
+            a += st;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < UL; ++j) {
+            const uint64_t i = (uint64_t)it * UL + j;
+            const vec4u *src = i < my_nv ? vp + (i << glog) : zero;
+            q[j] = *src;
+        }
+    }
+}
+
 // One lane group: 2^glog lanes share each segment (64 >> glog segments, the
 // first `count` valid).  Lane l reads every 2^glog-th 16-byte vector of
 // segment l >> glog, starting at vector l mod 2^glog, into its own column, so
@@ -304,20 +374,15 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
                                                const vec4u *zero, int lane)
 {
     using G = Geo<FMT>;
-    const uint32_t sub = (uint32_t)lane & ((1u << glog) - 1);
-    const bool live = ((uint32_t)lane >> glog) < count;
+    constexpr uint32_t kLog2Bytes = FMT == XSUM_F64 ? 3 : FMT == XSUM_F32 ? 2 : 1;
+    const LaneShare sh = lane_share(base, e, count, glog, kLog2Bytes, lane);
+    const uint32_t sub = sh.sub;
+    const bool live = sh.live;
     const uint32_t s = e.seg;
-    const uint64_t off = live ? e.byte_offset : 0;
-    const uint64_t L = live ? e.length : 0;
-    const uint8_t *p = base + off;
-    uint64_t head = ((16 - ((uintptr_t)p & 15)) & 15) / G::kBytes;
-    if (head > L)
-        head = L;
-    const uint64_t nv = (L - head) / G::kPerVec;
-    const uint64_t tail = L - head - nv * G::kPerVec;
-    const vec4u *vp = (const vec4u *)(p + head * G::kBytes) + sub;
-    // this lane's vectors: sub, sub + 2^glog, ...
-    const uint64_t my_nv = nv > sub ? ((nv - sub - 1) >> glog) + 1 : 0;
+    const uint8_t *p = sh.p;
+    const uint64_t head = sh.head, nv = sh.nv, tail = sh.tail;
+    const vec4u *vp = sh.vp;
+    const uint64_t my_nv = sh.my_nv;
     uint32_t spec = 0;
     uint32_t kmin = 0xffffffffu, kmax = 0;
 
@@ -329,21 +394,26 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
     // each lane walks its share of its segment, UL vectors per step, the next
     // step's loads in flight while the current step is added
     vec4u qa[UL], qb[UL];
-    // Every lane loads on every step (no load sits in a branch, so the
-    // compiler's wait counts keep the spare buffer's loads in flight): a
-    // lane past the end of its share, or a step past the last, loads the
-    // zero vector instead (and leaves it out of its row bounds).
+    auto step_rem = [&](uint32_t it) -> int64_t {
+        return (int64_t)my_nv - (int64_t)it * UL;
+    };
+    auto uniform_step = [&](int64_t rem) -> bool {
+        return __ballot(rem > 0 && rem < UL) == 0;
+    };
     auto load_step = [&](vec4u (&q)[UL], uint32_t it) {
-#pragma unroll
-        for (int j = 0; j < UL; ++j) {
-            const uint64_t i = (uint64_t)it * UL + j;
-            const vec4u *src = i < my_nv ? vp + (i << glog) : zero;
-            q[j] = *src;    // cached: neighbouring loads share lines
-        }
+        load_lane_step<UL>(q, vp, my_nv, it, glog, zero);
     };
     auto add_step = [&](const vec4u (&q)[UL], uint32_t it) {
-        const uint64_t done = (uint64_t)it * UL;
-        track_keys<FMT, UL>(q, my_nv > done ? my_nv - done : 0, kmin, kmax);
+        const int64_t rem = step_rem(it);
+        if (uniform_step(rem)) {
+            // whole step or none: bounds of all UL vectors, kept or dropped
+            uint32_t smin = 0xffffffffu, smax = 0;
+            track_keys<FMT, UL>(q, UL, smin, smax);
+            kmin = min(kmin, rem > 0 ? smin : 0xffffffffu);
+            kmax = max(kmax, rem > 0 ? smax : 0u);
+        } else {
+            track_keys<FMT, UL>(q, rem > 0 ? (uint64_t)rem : 0, kmin, kmax);
+        }
         add_tile<FMT, UL>(q, col, spec);
         if constexpr (FMT == XSUM_F64) {
             if (++since >= kNormIters) {
