@@ -508,6 +508,18 @@ def bench_segmented(args):
     ms = timed_launches(lambda: xs.xsum_graph_launch(graph, sh), stream, args.warmup, steps)
     res = out.cpu().numpy().view(np.uint64)
     rf = fl.cpu().numpy().view(np.uint32)
+    # the binary64 segments alone, same buffer and tuning, also one graph
+    f64_desc = desc[desc["dtype"] == 0]
+    f64_bytes = int(f64_desc["length"].sum()) * 8
+    ss64 = xs.SegmentedSum(f64_desc, tuning=autotune.tuning_struct(best))
+    out64 = torch.zeros(len(f64_desc), dtype=torch.int64, device="cuda")
+    fl64 = torch.zeros(len(f64_desc), dtype=torch.int32, device="cuda")
+    g64 = ss64.capture(dbuf, out64, fl64)
+    ms64 = timed_launches(lambda: xs.xsum_graph_launch(g64, sh), stream, args.warmup, steps)
+    same64 = np.array_equal(out64.cpu().numpy().view(np.uint64),
+                            res[desc["dtype"] == 0])
+    xs.xsum_graph_destroy(g64)
+    ss64.close()
     # parity of every segment: the oracle's per-segment sums over the whole
     # buffer (exponent bins and a wide-integer fold in C, rounding in Python),
     # which is also the timed cpu_baseline leg
@@ -525,18 +537,6 @@ def bench_segmented(args):
     xs.xsum_graph_destroy(graph)
     info = ss.info
     ss.close()
-    # the binary64 segments alone, same buffer and tuning, also one graph
-    f64_desc = desc[desc["dtype"] == 0]
-    f64_bytes = int(f64_desc["length"].sum()) * 8
-    ss64 = xs.SegmentedSum(f64_desc, tuning=autotune.tuning_struct(best))
-    out64 = torch.zeros(len(f64_desc), dtype=torch.int64, device="cuda")
-    fl64 = torch.zeros(len(f64_desc), dtype=torch.int32, device="cuda")
-    g64 = ss64.capture(dbuf, out64, fl64)
-    ms64 = timed_launches(lambda: xs.xsum_graph_launch(g64, sh), stream, args.warmup, steps)
-    same64 = np.array_equal(out64.cpu().numpy().view(np.uint64),
-                            res[desc["dtype"] == 0])
-    xs.xsum_graph_destroy(g64)
-    ss64.close()
     achieved = nbytes / (ms * 1e-3) / 1e9
     rec = {"metric": "segmented exact sums Gelem/s + % HBM roofline (bit-exact)",
            "value": round(nel / (ms * 1e-3) / 1e9, 2), "unit": "Gelem/s",

@@ -15,7 +15,7 @@
 
 namespace xsum {
 hipError_t launch_segmented(const void *base, const SegDesc *segs,
-                            const SegTask *tasks, uint32_t ntasks, uint32_t small_from,
+                            const SegTask *tasks, uint32_t ntasks,
                             const SegLane *lanes, xsum_acc_t *states,
                             SegCtl *ctl, int out_mode, uint64_t *out,
                             uint32_t *flags, int blocks, hipStream_t stream);
@@ -48,7 +48,6 @@ struct xsum_plan {
     xsum::SegTask *d_tasks = nullptr;
     xsum::SegLane *d_lanes = nullptr;
     uint32_t ntasks = 0, nslots = 0;
-    uint32_t small_from = 0;  // first item that may be claimed with its neighbours
     int blocks = 0;
     xsum_plan_info_t info{};
 };
@@ -93,7 +92,6 @@ struct HostPlan {
     std::vector<xsum::SegTask> tasks;
     std::vector<xsum::SegLane> lanes;
     uint32_t nslots = 0;
-    uint32_t small_from = 0;
     int blocks = 0;
     xsum_plan_info_t info{};
 };
@@ -287,19 +285,6 @@ xsum_status_t make_plan(const xsum_segment_t *segs, uint64_t nseg, int out_dtype
 
     hp.nslots = slots;
     hp.blocks = xsum::segmented_blocks(cus, blocks_per_cu);
-    // Items are claimed one at a time while they are large (longest first is
-    // what balances the waves) and several at a time once an item is below
-    // 1/16 of a wave's share of the estimated work.
-    {
-        long double total = 0;
-        for (const HostTask &h : tasks)
-            total += (long double)h.cost;
-        const long double share = total / (long double)std::max(1, hp.blocks);
-        uint32_t i = 0;
-        while (i < (uint32_t)tasks.size() && (long double)tasks[i].cost * 16 >= share)
-            ++i;
-        hp.small_from = i;
-    }
     hp.info.nseg = nseg;
     hp.info.lane_segments = lane_ids[0].size() + lane_ids[1].size() + lane_ids[2].size();
     hp.info.wave_segments = wave_ids.size();
@@ -364,7 +349,6 @@ xsum_status_t xsum_segmented_plan(const xsum_segment_t *segs, uint64_t nseg,
     p->out_mode = out_dtype;
     p->ntasks = (uint32_t)hp.tasks.size();
     p->nslots = hp.nslots;
-    p->small_from = hp.small_from;
     p->blocks = hp.blocks;
     p->info = hp.info;
     const std::vector<xsum::SegTask> &flat = hp.tasks;
@@ -487,7 +471,7 @@ xsum_status_t xsum_exact_sum_segmented(const void *base, const xsum_segment_t *s
     if (e == hipSuccess)
         e = xsum::launch_segmented(base, (const xsum::SegDesc *)(ws + L.segs),
                                    (const xsum::SegTask *)(ws + L.tasks),
-                                   (uint32_t)hp.tasks.size(), hp.small_from,
+                                   (uint32_t)hp.tasks.size(),
                                    (const xsum::SegLane *)(ws + L.lanes),
                                    (xsum_acc_t *)(ws + xsum::kSegCtlBytes), (xsum::SegCtl *)ws,
                                    out_dtype, (uint64_t *)out, flags, hp.blocks, s);
@@ -518,7 +502,7 @@ xsum_status_t xsum_segmented_run(const xsum_plan_t *plan, const void *base,
     if (dev != plan->device)
         return api_fail(XSUM_EINVAL, "plan was built for another device");
     uint8_t *ws = (uint8_t *)workspace;
-    e = xsum::launch_segmented(base, plan->d_segs, plan->d_tasks, plan->ntasks, plan->small_from,
+    e = xsum::launch_segmented(base, plan->d_segs, plan->d_tasks, plan->ntasks,
                                plan->d_lanes, (xsum_acc_t *)(ws + xsum::kSegCtlBytes),
                                (xsum::SegCtl *)ws, plan->out_mode, (uint64_t *)out,
                                flags, plan->blocks, (hipStream_t)stream);

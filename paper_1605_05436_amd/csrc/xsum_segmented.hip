@@ -34,8 +34,6 @@
 
 namespace xsum {
 
-// Work items claimed per queue atomic by the segmented kernel.
-static constexpr int kSegPopBatch = 4;
 
 template <int FMT> struct LaneOut;
 template <> struct LaneOut<XSUM_F64> { static constexpr int kNatural = XSUM_F64; };
@@ -712,7 +710,7 @@ __device__ __forceinline__ SegLane lane_entry(const SegLane *__restrict__ lanes,
 template <int WAVES, int UL, int UC>
 __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
     const uint8_t *__restrict__ base, const SegDesc *__restrict__ segs,
-    const SegTask *__restrict__ tasks, uint32_t ntasks, uint32_t small_from,
+    const SegTask *__restrict__ tasks, uint32_t ntasks,
     const SegLane *__restrict__ lanes, xsum_acc_t *states, SegCtl *ctl,
     int out_mode, uint64_t *out, uint32_t *flags)
 {
@@ -722,55 +720,26 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
     uint64_t *col = &w.cols[0][lane];
     zero_column<XSUM_F64>(col);
 
-    // Items are claimed from the queue one at a time while they are large
-    // (longest first is what balances the waves), and kSegPopBatch at a time
-    // from item small_from on, where items are short.  The next claim is made
-    // while the current one is handed out: a device-scope atomic's round trip
-    // is long and its result is waited for where it is taken, so one wait
-    // then serves several short items.
-    uint32_t b0 = 0, n0 = 1, b1 = 0, n1 = 1, bi = 0;
-    if (lane == 0) {
-        b0 = atomicAdd(&ctl->head, 1u);
-        b1 = atomicAdd(&ctl->head, 1u);
-    }
-    b0 = __shfl(b0, 0, 64);
-    b1 = __shfl(b1, 0, 64);
-    // next item index; each wave's indices only grow, so the first one past
-    // the end ends the wave's work
-    auto draw = [&]() -> uint32_t {
-        if (bi == n0) {
-            b0 = b1;
-            n0 = n1;
-            bi = 0;
-            n1 = b0 >= small_from ? (uint32_t)kSegPopBatch : 1u;
-            uint32_t claimed = 0;
-            if (lane == 0)
-                claimed = atomicAdd(&ctl->head, n1);
-            b1 = __shfl(claimed, 0, 64);
-        }
-        return b0 + bi++;
+    // Items are claimed from the queue one at a time, one item ahead: the
+    // claim of the item after next is issued when an item starts, so its
+    // round trip (a device-scope atomic takes microseconds) is hidden behind
+    // a whole item, and a wave never holds more than the item it runs and
+    // the one it has claimed.  Holding more (deeper prefetch, claims of
+    // several short items at once) left waves idle at the end of the queue
+    // while others still worked through items they had reserved.
+    auto claim = [&]() -> uint32_t {
+        uint32_t c = 0;
+        if (lane == 0)
+            c = atomicAdd(&ctl->head, 1u);
+        return __shfl(c, 0, 64);
     };
-
-    // Work items flow through a three-stage pipeline so that no dependent
-    // global access stands between two items: while item i runs, the record
-    // and lane entry of item i + 1 and the record of item i + 2 are already
-    // in registers or in flight.
-    uint32_t cur = draw();
-    uint32_t next = draw();
-    uint32_t after = draw();
-    SegTask t{}, nt{};
+    uint32_t cur = claim();
+    uint32_t next = claim();
+    SegTask t{};
     if (cur < ntasks)
         t = tasks[cur];
-    if (next < ntasks)
-        nt = tasks[next];
     SegLane e = lane_entry(lanes, t, cur < ntasks, lane);
     while (cur < ntasks) {
-        // issued before the item's own loads, consumed at the next item
-        const SegLane ne = lane_entry(lanes, nt, next < ntasks, lane);
-        SegTask nnt{};
-        if (after < ntasks)
-            nnt = tasks[after];
-        const uint32_t following = draw();
         const uint32_t kind = t.kind_dtype_flags & 0xffu;
         const uint32_t dtype = (t.kind_dtype_flags >> 8) & 0xffu;
         if (kind == kLaneGroup) {
@@ -812,11 +781,15 @@ __global__ __launch_bounds__(WAVES * 64) void segmented_kernel(
             else
                 run_chunk<XSUM_BF16, UC>(base, segs, t, states, w, col, out_mode, out, flags, lane);
         }
+        // the next item's record and lane entry, then the claim after it
+        SegTask nt{};
+        if (next < ntasks)
+            nt = tasks[next];
+        const SegLane ne = lane_entry(lanes, nt, next < ntasks, lane);
+        const uint32_t following = claim();
         cur = next;
-        next = after;
-        after = following;
+        next = following;
         t = nt;
-        nt = nnt;
         e = ne;
     }
     // The last wave out resets the queue for the next launch.  Every wave's
@@ -956,14 +929,14 @@ int segmented_blocks(int cu_count, int blocks_per_cu)
 }
 
 hipError_t launch_segmented(const void *base, const SegDesc *segs,
-                            const SegTask *tasks, uint32_t ntasks, uint32_t small_from,
+                            const SegTask *tasks, uint32_t ntasks,
                             const SegLane *lanes, xsum_acc_t *states,
                             SegCtl *ctl, int out_mode, uint64_t *out,
                             uint32_t *flags, int blocks, hipStream_t stream)
 {
     hipLaunchKernelGGL((segmented_kernel<kSegWaves, kSegLaneUnroll, kSegChunkUnroll>),
                        dim3((unsigned)blocks), dim3(kSegWaves * 64), 0, stream,
-                       (const uint8_t *)base, segs, tasks, ntasks, small_from, lanes, states,
+                       (const uint8_t *)base, segs, tasks, ntasks, lanes, states,
                        ctl, out_mode, out, flags);
     return hipGetLastError();
 }
