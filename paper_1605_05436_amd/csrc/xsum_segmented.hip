@@ -186,17 +186,96 @@ __device__ __forceinline__ void track_keys(const vec4u (&q)[U], uint64_t nvalid,
     }
 }
 
-// The key of one element read with a scalar load.
+// One element given as its bit pattern (read earlier with a scalar load):
+// added like add_scalar adds one read in place.
 template <int FMT>
-__device__ __forceinline__ uint32_t scalar_key(const uint8_t *p)
+__device__ __forceinline__ void add_element(uint64_t bits, uint64_t *col, uint32_t &spec)
+{
+    uint32_t emax = 0;
+    if constexpr (FMT == XSUM_F64) {
+        const uint32_t lo = (uint32_t)bits, hi = (uint32_t)(bits >> 32);
+        add_f64(lo, hi, col, emax);
+        fix_f64(lo, hi, col, spec);
+    } else if constexpr (FMT == XSUM_F32) {
+        add_f32((uint32_t)bits, col, emax);
+        fix_f32((uint32_t)bits, col, spec);
+    } else {
+        u16x2 em = (u16x2)0;
+        add_bf16_pair((uint32_t)bits, col, em);    // upper half +0, adds 0
+        fix_bf16_pair((uint32_t)bits, col, spec);
+    }
+}
+
+template <int FMT>
+__device__ __forceinline__ uint64_t load_element(const uint8_t *p)
 {
     if constexpr (FMT == XSUM_F64)
-        return (((const uint32_t *)p)[1] >> 20) & 0x7ffu;
+        return *(const uint64_t *)p;
     else if constexpr (FMT == XSUM_F32)
-        return *(const uint32_t *)p & 0x7fffffffu;
+        return *(const uint32_t *)p;
     else
-        return (uint32_t)(*(const uint16_t *)p) & 0x7fffu;
+        return *(const uint16_t *)p;
 }
+
+// The key (exponent field or magnitude bits) of an element's bit pattern.
+template <int FMT>
+__device__ __forceinline__ uint32_t element_key(uint64_t bits)
+{
+    if constexpr (FMT == XSUM_F64)
+        return (uint32_t)(bits >> 52) & 0x7ffu;
+    else if constexpr (FMT == XSUM_F32)
+        return (uint32_t)bits & 0x7fffffffu;
+    else
+        return (uint32_t)bits & 0x7fffu;
+}
+
+// The elements of a segment outside its 16-byte vectors: the unaligned head
+// and the ragged tail, fewer than one vector's worth each.  They are loaded
+// when the work item starts, so their loads are in flight while the vectors
+// stream, and added from registers at the end.
+template <int FMT>
+struct EdgeElems {
+    static constexpr int kMax = 16 / Geo<FMT>::kBytes - 1;   // 1, 3 or 7
+    uint64_t h[kMax], t[kMax];
+    uint32_t nh, nt;
+
+    __device__ __forceinline__ void load(const uint8_t *p, uint64_t head, uint64_t nv,
+                                         uint64_t tail)
+    {
+        nh = (uint32_t)head;
+        nt = (uint32_t)tail;
+        const uint8_t *tp = p + head * Geo<FMT>::kBytes + nv * 16;
+#pragma unroll
+        for (int i = 0; i < kMax; ++i) {
+            h[i] = 0;
+            t[i] = 0;
+            if ((uint32_t)i < nh)
+                h[i] = load_element<FMT>(p + i * Geo<FMT>::kBytes);
+            if ((uint32_t)i < nt)
+                t[i] = load_element<FMT>(tp + i * Geo<FMT>::kBytes);
+        }
+    }
+
+    __device__ __forceinline__ void add(uint64_t *col, uint32_t &spec, uint32_t &kmin,
+                                        uint32_t &kmax)
+    {
+#pragma unroll
+        for (int i = 0; i < kMax; ++i) {
+            if ((uint32_t)i < nh) {
+                const uint32_t k = element_key<FMT>(h[i]);
+                kmin = min(kmin, k);
+                kmax = max(kmax, k);
+                add_element<FMT>(h[i], col, spec);
+            }
+            if ((uint32_t)i < nt) {
+                const uint32_t k = element_key<FMT>(t[i]);
+                kmin = min(kmin, k);
+                kmax = max(kmax, k);
+                add_element<FMT>(t[i], col, spec);
+            }
+        }
+    }
+};
 
 // Carry step over rows [r0, r1) of a binary64 column: every row but the last
 // keeps its low 32 bits, its carry goes to the row above; the carries of row
@@ -383,6 +462,8 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
     const uint64_t my_nv = sh.my_nv;
     uint32_t spec = 0;
     uint32_t kmin = 0xffffffffu, kmax = 0;
+    EdgeElems<FMT> edges;
+    edges.load(p, sub == 0 ? head : 0, nv, sub == 0 ? tail : 0);
 
     const uint64_t my_iters = (my_nv + UL - 1) / UL;
     const uint32_t iters = wave_max_u32((uint32_t)my_iters);
@@ -435,21 +516,7 @@ __device__ __forceinline__ void run_lane_group(const uint8_t *base, const SegLan
         load_step(qa, it + 2);
         add_step(qb, it + 1);
     }
-    if (sub == 0) {
-        for (uint64_t i = 0; i < head; ++i) {
-            const uint32_t k = scalar_key<FMT>(p + i * G::kBytes);
-            kmin = min(kmin, k);
-            kmax = max(kmax, k);
-            add_scalar<FMT>(p + i * G::kBytes, col, spec);
-        }
-        const uint8_t *tp = p + head * G::kBytes + nv * 16;
-        for (uint64_t i = 0; i < tail; ++i) {
-            const uint32_t k = scalar_key<FMT>(tp + i * G::kBytes);
-            kmin = min(kmin, k);
-            kmax = max(kmax, k);
-            add_scalar<FMT>(tp + i * G::kBytes, col, spec);
-        }
-    }
+    edges.add(col, spec, kmin, kmax);
     // the rows this lane may have written: binary64 also the carry row above
     // the highest touched one
     int r0 = G::kN, r1 = 0;
@@ -524,6 +591,12 @@ __device__ __forceinline__ void accumulate_span(const vec4u *vp, uint64_t nv,
     constexpr int kNormTiles = 512 / UC;
     const uint64_t full = nv / kTile;
     int since = 0;
+    // one head and one tail element per lane, loaded now, added at the end
+    uint64_t hv = 0, tv = 0;
+    if ((uint64_t)lane < head)
+        hv = load_element<FMT>(head_p + (uint64_t)lane * G::kBytes);
+    if ((uint64_t)lane < tail)
+        tv = load_element<FMT>(tail_p + (uint64_t)lane * G::kBytes);
     if (full > 0) {
         // The next tile's loads are issued on every pass: past the span's
         // last full tile every one of them re-reads the lane's vector of the
@@ -574,9 +647,9 @@ __device__ __forceinline__ void accumulate_span(const vec4u *vp, uint64_t nv,
         add_tile<FMT, UC>(q, col, spec);
     }
     if ((uint64_t)lane < head)
-        add_scalar<FMT>(head_p + (uint64_t)lane * G::kBytes, col, spec);
+        add_element<FMT>(hv, col, spec);
     if ((uint64_t)lane < tail)
-        add_scalar<FMT>(tail_p + (uint64_t)lane * G::kBytes, col, spec);
+        add_element<FMT>(tv, col, spec);
 }
 
 // Merge the wave's 64 columns into w.merged, then clear the columns.
