@@ -157,6 +157,8 @@ def main():
     ap.add_argument("--nseg", type=int, default=1_000_000)
     ap.add_argument("--duration", type=float, default=60.0)
     ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="segmented workload: use the library's default tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run one device copy of the input "
                          "(a plain copy kernel of known size, for scaling "
@@ -493,7 +495,10 @@ def bench_segmented(args):
     # and vectors in flight per format and size bucket
     from paper_1605_05436_amd import autotune
     t0 = time.time()
-    best, table = autotune.tune_segmented(desc, dbuf, use_cache=False)
+    if args.no_autotune:
+        best, table = autotune._full(autotune.DEFAULT_CANDIDATES[0]), []
+    else:
+        best, table = autotune.tune_segmented(desc, dbuf, use_cache=False)
     tune_s = time.time() - t0
     log("autotune done in %.1f s" % tune_s)
     t0 = time.time()
@@ -537,6 +542,13 @@ def bench_segmented(args):
     xs.xsum_graph_destroy(graph)
     info = ss.info
     ss.close()
+    copy_note = None
+    if args.copy_calibration:
+        y = torch.empty_like(dbuf)
+        y.copy_(dbuf)
+        torch.cuda.synchronize()
+        copy_note = {"read": int(dbuf.numel()), "write": int(dbuf.numel())}
+        del y
     achieved = nbytes / (ms * 1e-3) / 1e9
     rec = {"metric": "segmented exact sums Gelem/s + % HBM roofline (bit-exact)",
            "value": round(nel / (ms * 1e-3) / 1e9, 2), "unit": "Gelem/s",
@@ -569,6 +581,8 @@ def bench_segmented(args):
                         "traffic": measured_traffic(
                             nel, SEG_KERNEL_SOURCES, SEG_TRAFFIC_PROFILE,
                             {"tuning": autotune._as_list(best)})}}
+    if copy_note:
+        rec["copy_calibration_bytes"] = copy_note
     print(json.dumps(rec), flush=True)
 
 
