@@ -45,3 +45,5 @@ __all__ = [
     "value_fraction", "exact_sum_binned", "oracle_sum_binned", "build_binned",
     "segmented_exact_sums", "segmented_oracle_sums",
 ]
+from . import truncated
+from .truncated import adaptive_sum
