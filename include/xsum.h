@@ -225,6 +225,76 @@ xsum_status_t xsum_exact_sum_host(const void *x_host, uint64_t n, int dtype,
                                   uint64_t chunk_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Condition-number-sensitive sum (Section 4): the input is summed with
+ * r-truncated sparse superaccumulators up a summation tree, the root is
+ * tested, and r is squared (2, 4, 16) until the test passes.  r = 256 would
+ * exceed the 68 digit positions, so that pass truncates nothing and is the
+ * exact sum itself.  The test certifies the round-to-nearest-even result (the
+ * same bits and flags as xsum_exact_sum), not only a faithful one.
+ * ------------------------------------------------------------------------ */
+
+#define XSUM_TRUNC_MAX_R 16
+
+/* Root of one truncated pass (device memory, written by the pass).
+ *   index/value  the root's entries, most significant first: `count` of
+ *                them, each worth value * 2^(32 index - 1074); value is the
+ *                exact integer sum of the radix-2^32 digits added at that
+ *                index (not carry-normalised).  Unused entries have a
+ *                negative index and value 0.
+ *   bound_index/bound_value  everything truncated anywhere on the tree sums
+ *                to at most bound_value * 2^(32 bound_index - 1074) in
+ *                magnitude; bound_value 0 means nothing was lost.
+ *   special      NaN (bit 0), +inf (bit 1), -inf (bit 2) inputs seen.
+ *   certified    1: bits/flags hold the round-to-nearest-even sum (bit
+ *                pattern zero-extended to 64 bits); 0: the pass cannot tell.
+ *   r            the truncation parameter of the pass. */
+typedef struct xsum_trunc_root {
+    int32_t index[XSUM_TRUNC_MAX_R];
+    int64_t value[XSUM_TRUNC_MAX_R];
+    uint32_t count;
+    int32_t bound_index;
+    uint64_t bound_value;
+    uint32_t special;
+    uint32_t certified;
+    uint64_t bits;
+    uint32_t flags;
+    uint32_t r;
+} xsum_trunc_root_t;
+
+/* Device workspace bytes of the calls below (fixed, about 0.5 MiB). */
+size_t xsum_truncated_workspace_size(void);
+
+/*
+ * One pass with truncation parameter r (2, 4 or 16), asynchronous, one
+ * kernel launch (Section 4, the bottom-up merge-and-sum with r-truncated
+ * sparse superaccumulators, Lemma 3 for each pairwise sum, and the stopping
+ * test on the root).
+ *   x, n, dtype, out_dtype  as for xsum_exact_sum; n <= 2^31 (XSUM_ERANGE)
+ *   root_dev   device, receives the pass's xsum_trunc_root_t
+ *   workspace  device, 256-byte aligned, xsum_truncated_workspace_size()
+ *              bytes, zero-filled before its first use; every pass leaves
+ *              it as it found it.  Calls sharing a workspace must be ordered.
+ * The record does not depend on scheduling: the tree's shape is fixed by n,
+ * the input's address and the device's compute-unit count.
+ */
+xsum_status_t xsum_truncated_round(const void *x, uint64_t n, int dtype, int out_dtype,
+                                   int r, xsum_trunc_root_t *root_dev, void *workspace,
+                                   size_t ws_bytes, void *stream);
+
+/*
+ * The whole iteration, blocking: passes with r = 2, 4, 16 until one is
+ * certified, else the untruncated pass (the exact-sum kernel).  Writes the
+ * result bit pattern to out_host (8, 4 or 2 bytes), flags to flags_host (may
+ * be NULL) and the r of the certifying pass to r_host (may be NULL; 0 when the
+ * untruncated pass gave the result).  The result equals xsum_exact_sum's.
+ * workspace as for xsum_truncated_round; the call zero-fills it first.  Reads
+ * each pass's record back, so it cannot be captured into a graph.
+ */
+xsum_status_t xsum_exact_sum_truncated(const void *x, uint64_t n, int dtype, int out_dtype,
+                                       void *out_host, uint32_t *flags_host, int *r_host,
+                                       void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Segmented sums: many independent exact sums of uneven lengths and mixed
  * formats in one persistent kernel launch (Section 6: each reducer sums its
  * own inputs into a superaccumulator; long inputs are summed per chunk and

@@ -38,6 +38,8 @@ EXPORTED = [
     "xsum_segmented_run", "xsum_segmented_run_noalloc", "xsum_segmented_capture", "xsum_graph_launch",
     "xsum_graph_destroy", "xsum_batch_item_tasks", "xsum_batch_add",
     "xsum_batch_finalize", "xsum_probe_read", "xsum_probe_flush",
+    "xsum_truncated_workspace_size", "xsum_truncated_round",
+    "xsum_exact_sum_truncated",
 ]
 
 # xsum_batch_item_t as a numpy record (32 bytes)
@@ -55,6 +57,19 @@ class SegTuning(ctypes.Structure):
                 ("two_lanes_from", ctypes.c_uint64), ("four_lanes_from", ctypes.c_uint64),
                 ("lanes", (ctypes.c_uint8 * TUNE_BUCKETS) * 3),
                 ("lane_unroll", (ctypes.c_uint8 * TUNE_BUCKETS) * 3)]
+
+
+TRUNC_MAX_R = 16
+
+
+class TruncRoot(ctypes.Structure):
+    """xsum_trunc_root_t: the root of one truncated pass."""
+    _fields_ = [("index", ctypes.c_int32 * TRUNC_MAX_R),
+                ("value", ctypes.c_int64 * TRUNC_MAX_R),
+                ("count", ctypes.c_uint32), ("bound_index", ctypes.c_int32),
+                ("bound_value", ctypes.c_uint64), ("special", ctypes.c_uint32),
+                ("certified", ctypes.c_uint32), ("bits", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("r", ctypes.c_uint32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -175,6 +190,14 @@ def _load():
     lib.xsum_probe_read.argtypes = [vp, u64, vp, vp]
     lib.xsum_probe_flush.restype = i32
     lib.xsum_probe_flush.argtypes = [vp, u64, ctypes.c_uint32, vp]
+    lib.xsum_truncated_workspace_size.restype = ctypes.c_size_t
+    lib.xsum_truncated_workspace_size.argtypes = []
+    lib.xsum_truncated_round.restype = i32
+    lib.xsum_truncated_round.argtypes = [vp, u64, i32, i32, i32, vp, vp, ctypes.c_size_t, vp]
+    lib.xsum_exact_sum_truncated.restype = i32
+    lib.xsum_exact_sum_truncated.argtypes = [vp, u64, i32, i32, vp, u32p,
+                                             ctypes.POINTER(ctypes.c_int), vp,
+                                             ctypes.c_size_t, vp]
     return lib
 
 
@@ -400,6 +423,36 @@ def xsum_probe_flush(buf, nbytes, value=0, stream=0):
 
 
 # ----------------------------------------------------- torch marshalling --
+
+def xsum_truncated_workspace_size():
+    return _lib.xsum_truncated_workspace_size()
+
+
+def xsum_truncated_round(x, n, dtype, out_dtype, r, root, ws, ws_bytes, stream=0):
+    """One Section 4 pass with truncation parameter r; writes the root record
+    (TruncRoot layout) to device address root."""
+    _check(_lib.xsum_truncated_round(_p(x), n, dtype, out_dtype, r, _p(root), _p(ws),
+                                     ws_bytes, _p(stream)))
+
+
+def xsum_exact_sum_truncated(x, n, dtype, out_dtype, ws, ws_bytes, stream=0):
+    """Blocking Section 4 iteration.  Returns (result bit pattern, flags, r of
+    the certifying pass or 0 for the untruncated one)."""
+    out = ctypes.c_uint64(0)
+    flags = ctypes.c_uint32(0)
+    r = ctypes.c_int(-1)
+    _check(_lib.xsum_exact_sum_truncated(_p(x), n, dtype, out_dtype, ctypes.byref(out),
+                                         ctypes.byref(flags), ctypes.byref(r), _p(ws),
+                                         ws_bytes, _p(stream)))
+    ob = OUT_BYTES[(F64 if dtype == F64 else F32) if out_dtype == SAME else out_dtype]
+    return out.value & ((1 << (8 * ob)) - 1), flags.value, r.value
+
+
+def read_trunc_root(dev_tensor):
+    """TruncRoot from the device bytes of a record (a uint8 CUDA tensor)."""
+    raw = bytes(dev_tensor.cpu().numpy().tobytes())
+    return TruncRoot.from_buffer_copy(raw[:ctypes.sizeof(TruncRoot)])
+
 
 def stream_handle(stream=None):
     """Raw hipStream_t of a torch stream (default: the current stream)."""

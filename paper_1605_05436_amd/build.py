@@ -13,6 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libxsum.so")
 SOURCES = ["xsum_kernels.hip", "xsum_segmented.hip", "xsum_plan.hip", "xsum_api.hip",
+           "xsum_truncated.hip",
            "xsum_stream.hip", "xsum_state.hip", "xsum_probe.hip"]
 HEADERS = ["xsum_device.h", "xsum_internal.h", "xsum_segmented.h", "xsum_host.h"]
 ARCH = os.environ.get("XSUM_OFFLOAD_ARCH", "gfx950")

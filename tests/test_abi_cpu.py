@@ -222,3 +222,64 @@ def test_segmented_workspace_bound_grows_with_the_batch(lib):
     for nseg, total in [(10, 100), (10**6, 2 * 10**9), (5, 1 << 40)]:
         assert f(nseg, total) <= f(nseg + 1, total) <= f(nseg + 1, total + (1 << 20))
     assert f(1 << 31, 0) == 0 and f(1, 1 << 51) == 0
+
+
+def test_truncated_pass_rejects_bad_arguments_on_the_host(lib):
+    vp = ctypes.c_void_p
+    ws = lib.xsum_truncated_workspace_size
+    ws.restype = ctypes.c_size_t
+    ws.argtypes = []
+    nbytes = ws()
+    # control word, 2048 block slots of 256 bytes, the record, an exact state
+    assert nbytes == 256 + 2048 * 256 + 256 + 768
+    f = lib.xsum_truncated_round
+    f.restype = ctypes.c_int
+    f.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp,
+                  ctypes.c_size_t, vp]
+    good = (4096, 8, 0, 255, 2, 8192, 1 << 20, nbytes, None)
+    for r in (0, 1, 3, 8, 256):
+        assert f(*good[:4], r, *good[5:]) == 1
+    assert "r must be" in _err(lib)
+    assert f(4096, 8, 7, 255, 2, 8192, 1 << 20, nbytes, None) == 2
+    assert f(4096, 8, 0, 9, 2, 8192, 1 << 20, nbytes, None) == 2
+    assert f(None, 8, 0, 255, 2, 8192, 1 << 20, nbytes, None) == 1
+    assert f(4100, 8, 0, 255, 2, 8192, 1 << 20, nbytes, None) == 1
+    assert f(4096, 8, 0, 255, 2, None, 1 << 20, nbytes, None) == 1
+    assert f(4096, 8, 0, 255, 2, 8192, (1 << 20) + 64, nbytes, None) == 1
+    assert f(4096, 8, 0, 255, 2, 8192, 1 << 20, nbytes - 8, None) == 1
+    assert f(4096, (1 << 31) + 1, 0, 255, 2, 8192, 1 << 20, nbytes, None) == 5
+    g = lib.xsum_exact_sum_truncated
+    g.restype = ctypes.c_int
+    g.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp,
+                  ctypes.c_size_t, vp]
+    assert g(4096, 8, 0, 255, None, None, None, 1 << 20, nbytes, None) == 1
+    assert g(4096, 8, 0, 255, 8192, None, None, None, nbytes, None) == 1
+
+
+def test_truncated_record_layout_matches_the_header(tmp_path):
+    import shutil
+    import subprocess
+    import paper_1605_05436_amd as xs
+    if shutil.which("gcc") is None:
+        pytest.skip("no host compiler")
+    src = tmp_path / "trunc.c"
+    src.write_text(r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "xsum.h"
+int main(void) {
+    printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(xsum_trunc_root_t),
+           offsetof(xsum_trunc_root_t, value), offsetof(xsum_trunc_root_t, count),
+           offsetof(xsum_trunc_root_t, bound_value), offsetof(xsum_trunc_root_t, certified),
+           offsetof(xsum_trunc_root_t, bits), offsetof(xsum_trunc_root_t, r));
+    return 0;
+}
+''')
+    exe = tmp_path / "trunc"
+    subprocess.run(["gcc", "-std=c11", "-I" + os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True,
+                                       check=True).stdout.split()))
+    T = xs.TruncRoot
+    assert got == [ctypes.sizeof(T), T.value.offset, T.count.offset, T.bound_value.offset,
+                   T.certified.offset, T.bits.offset, T.r.offset]
