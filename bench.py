@@ -153,7 +153,11 @@ def main():
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the read-probe and cold-cache legs")
     ap.add_argument("--workload", default="config3",
-                    choices=["config3", "single", "config1", "segmented", "serving"])
+                    choices=["config3", "single", "config1", "segmented", "serving",
+                             "truncated"])
+    ap.add_argument("--trunc-input", default="config3", choices=["config3", "config2"],
+                    help="input of the 'truncated' workload: the 2^31 binary64 "
+                         "headline input, or the 2^28 cancelling-pairs input")
     ap.add_argument("--nseg", type=int, default=1_000_000)
     ap.add_argument("--duration", type=float, default=60.0)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -177,6 +181,8 @@ def main():
         return bench_config1(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "truncated":
+        return bench_truncated(args)
     return bench_single(args)
 
 
@@ -389,6 +395,101 @@ def bench_single(args):
                                "sample_1core": "the first %d elements on 1 thread, "
                                                "accumulation only" % m1}
     print(json.dumps(rec), flush=True)
+
+
+def bench_truncated(args):
+    """Section 4's condition-number-sensitive iteration on one large input
+    resident in HBM: each pass (r = 2, 4, 16) timed on its own with HIP events,
+    then the whole blocking iteration (passes until one certifies, else the
+    exact kernel), whose result is checked against the oracle."""
+    import torch
+    import paper_1605_05436_amd as xs
+    import workloads
+    import oracle
+
+    t0 = time.time()
+    terms = None
+    if args.trunc_input == "config3":
+        n = 1 << 31
+        bits = workloads.config3(n=n, seed=args.seed)
+        workload = ("Section 4 iteration, n=2^31 binary64 N(0,1)*2^k, k in [-500,500], "
+                    "0.1% subnormal/+-DBL_MAX (balanced)")
+    else:
+        n = 1 << 28
+        bits, terms = workloads.config2(log2n=28, seed=args.seed)
+        workload = ("Section 4 iteration, n=2^28 binary64, cancelling pairs + 1% "
+                    "perturbations, seeded shuffle")
+    log("generated %d elements in %.1f s" % (n, time.time() - t0))
+    x = torch.from_numpy(bits.view(np.int64)).to("cuda")
+    wsb = xs.xsum_truncated_workspace_size()
+    ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda")
+    rec = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    sh = xs.stream_handle(stream)
+    torch.cuda.synchronize()
+    passes = {}
+    for r in (2, 4, 16):
+        ms = timed_launches(lambda: xs.xsum_truncated_round(
+            x.data_ptr(), n, xs.F64, xs.F64, r, rec.data_ptr(), ws.data_ptr(), wsb, sh),
+            stream, max(1, args.warmup // 4), max(1, args.steps // 4))
+        root = xs.read_trunc_root(rec)
+        passes[r] = {"ms": round(ms, 4), "gb_s": round(n * 8 / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(n * 8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "certified": bool(root.certified), "root_entries": int(root.count),
+                     "bound_log2": (None if root.bound_value == 0 else
+                                    32 * root.bound_index - 1074 +
+                                    root.bound_value.bit_length() - 1)}
+        log("pass r=%d: %.3f ms, certified=%s" % (r, ms, passes[r]["certified"]))
+    # the blocking iteration, end to end (host reads each pass's record)
+    times, res = [], None
+    for i in range(max(3, args.steps // 8)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = xs.xsum_exact_sum_truncated(x.data_ptr(), n, xs.F64, xs.F64, ws.data_ptr(),
+                                          wsb, sh)
+        times.append((time.perf_counter() - t1) * 1e3)
+    times.sort()
+    ms = times[len(times) // 2]
+    state = xs.new_states(1)
+    out = torch.zeros(2, dtype=torch.int64, device="cuda")
+    exact_ms = timed_launches(lambda: xs.xsum_exact_sum_async(
+        x.data_ptr(), n, xs.F64, xs.F64, out.data_ptr(), out.data_ptr() + 8,
+        state.data_ptr(), sh), stream, max(1, args.warmup // 4), max(1, args.steps // 4))
+    log("iteration: %.3f ms (median of %d), r=%d; exact kernel %.3f ms" % (ms, len(times), res[2], exact_ms))
+    (want_bits, want_flags), closed, threads, cpu_s, cpu_runs, log10_cond = \
+        cpu_baseline_full(bits, "f64", terms)
+    bit_exact = (res[0], res[1]) == (want_bits, want_flags) and closed
+    # the oracle's own Section 4 iteration (pure Python) on a bounded prefix
+    sample = 1 << 14
+    t1 = time.time()
+    o_res, o_passes, o_r = oracle.adaptive_sum(bits[:sample], "f64")
+    o_s = time.time() - t1
+    o_ok = tuple(o_res) == tuple(oracle.oracle_sum(bits[:sample], "f64"))
+    dominant = max(passes, key=lambda k: passes[k]["ms"] if (k <= (res[2] or 16)) else 0)
+    dp = passes[dominant]
+    rec_out = {
+        "metric": "exact FP64 sum Gelem/s, Section 4 condition-number-sensitive iteration (bit-exact)",
+        "value": round(n / (ms * 1e-3) / 1e9, 2), "unit": "Gelem/s", "n_gpus": 1,
+        "steps": len(times), "warmup": 1, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": workload, "n": n, "bytes": n * 8, "seed": args.seed},
+        "bit_exact": bool(bit_exact), "certified_r": res[2],
+        "passes": {str(k): v for k, v in passes.items()},
+        "exact_kernel_ms": round(exact_ms, 4), "log10_condition_number": log10_cond,
+        "cpu_baseline": {"value": round(sample / o_s / 1e9, 6), "unit": "Gelem/s", "cores": 1,
+                         "kind": "oracle",
+                         "sample": "first %d elements through the oracle's Section 4 "
+                                   "iteration (pure Python, balanced tree): %d passes, "
+                                   "r=%d, result equals the exact oracle: %s" % (
+                                       sample, o_passes, o_r, o_ok),
+                         "full_input_exact_oracle_s": round(cpu_s, 3),
+                         "full_input_exact_oracle_threads": threads},
+        "roofline": {"bound": "hbm", "achieved": dp["gb_s"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dp["frac_hbm"], "traffic": None,
+                     "kernel": "truncated_kernel r=%d" % dominant},
+    }
+    print(json.dumps(rec_out), flush=True)
 
 
 def bench_config1(args):
