@@ -62,6 +62,10 @@ SEG_KERNEL_SOURCES = ["paper_1605_05436_amd/csrc/xsum_segmented.hip",
                       "paper_1605_05436_amd/csrc/xsum_plan.hip",
                       "paper_1605_05436_amd/csrc/xsum_device.h"]
 SEG_TRAFFIC_PROFILE = "profiles/segmented_c4_1e6seg_hbm_counters.md"
+TRUNC_KERNEL_SOURCES = ["paper_1605_05436_amd/csrc/xsum_truncated.hip",
+                        "paper_1605_05436_amd/csrc/xsum_device.h"]
+TRUNC_TRAFFIC_PROFILES = {"config3": "profiles/truncated_f64_n2e31_hbm_counters.md",
+                          "config2": "profiles/truncated_f64_n2e28_hbm_counters.md"}
 
 
 def measured_traffic(n, sources=KERNEL_SOURCES, profile=TRAFFIC_PROFILE, match=None):
@@ -467,6 +471,11 @@ def bench_truncated(args):
     o_ok = tuple(o_res) == tuple(oracle.oracle_sum(bits[:sample], "f64"))
     dominant = max(passes, key=lambda k: passes[k]["ms"] if (k <= (res[2] or 16)) else 0)
     dp = passes[dominant]
+    if args.copy_calibration:
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del y
     rec_out = {
         "metric": "exact FP64 sum Gelem/s, Section 4 condition-number-sensitive iteration (bit-exact)",
         "value": round(n / (ms * 1e-3) / 1e9, 2), "unit": "Gelem/s", "n_gpus": 1,
@@ -477,6 +486,8 @@ def bench_truncated(args):
         "bit_exact": bool(bit_exact), "certified_r": res[2],
         "passes": {str(k): v for k, v in passes.items()},
         "exact_kernel_ms": round(exact_ms, 4), "log10_condition_number": log10_cond,
+        "copy_calibration_bytes": ({"read": n * 8, "write": n * 8}
+                                   if args.copy_calibration else None),
         "cpu_baseline": {"value": round(sample / o_s / 1e9, 6), "unit": "Gelem/s", "cores": 1,
                          "kind": "oracle",
                          "sample": "first %d elements through the oracle's Section 4 "
@@ -486,7 +497,10 @@ def bench_truncated(args):
                          "full_input_exact_oracle_s": round(cpu_s, 3),
                          "full_input_exact_oracle_threads": threads},
         "roofline": {"bound": "hbm", "achieved": dp["gb_s"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": dp["frac_hbm"], "traffic": None,
+                     "unit": "GB/s", "frac": dp["frac_hbm"],
+                     "traffic": measured_traffic(n, TRUNC_KERNEL_SOURCES,
+                                                 TRUNC_TRAFFIC_PROFILES[args.trunc_input],
+                                                 {"r": dominant}),
                      "kernel": "truncated_kernel r=%d" % dominant},
     }
     print(json.dumps(rec_out), flush=True)

@@ -229,11 +229,99 @@ __device__ __forceinline__ TList<R> tl_shfl_down(const TList<R> &L, int s)
 template <int R>
 __device__ __forceinline__ void tl_wave_merge(TList<R> &L, int lane, int width)
 {
+#pragma unroll 1
     for (int s = width >> 1; s >= 1; s >>= 1) {
         const TList<R> P = tl_shfl_down(L, s);
         if (lane < s)
             tl_merge(L, P);
     }
+}
+
+// A lane's list while it walks its elements.  To keep the per-entry update
+// to one select chain and one 64-bit add, a negative element adds the
+// complement ~d (= -d - 1) of its digit to the entries it touches and -1 to
+// every other entry; `negs` counts negative elements and base[j] is `negs`
+// when entry j was created, so the entry's true value is
+// val[j] + (negs - base[j]).  Elements dropped whole below the lowest entry
+// of a full list (each below one unit of that entry) are counted in `drops`
+// and moved into the bound whenever the lowest entry may change.
+template <int R>
+struct TWalk {
+    TList<R> L;
+    uint32_t base[R];
+    uint32_t negs;
+    uint32_t drops;
+    uint32_t spec;
+};
+
+template <int R>
+__device__ __forceinline__ void tw_init(TWalk<R> &W)
+{
+    tl_clear(W.L);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        W.base[j] = 0;
+    W.negs = 0;
+    W.drops = 0;
+    W.spec = 0;
+}
+
+template <int R>
+__device__ __forceinline__ void tw_flush_drops(TWalk<R> &W)
+{
+    if (W.drops) {
+        bound_add(W.L.bidx, W.L.bval, W.L.idx[R - 1], W.drops);
+        W.drops = 0;
+    }
+}
+
+// tl_insert on the biased list: the entry pushed out is bounded by its true
+// value, and the new entry (exact value v) starts unbiased.
+template <int R>
+__device__ __forceinline__ void tw_insert(TWalk<R> &W, int i, int64_t v)
+{
+    TList<R> &L = W.L;
+    const int lo = L.idx[R - 1];
+    const bool full = lo != kNoIdx;
+    if (full && i < lo) {
+        bound_add(L.bidx, L.bval, i, mag64(v));
+        return;
+    }
+    if (full)
+        bound_add(L.bidx, L.bval, lo,
+                  mag64(add64(L.val[R - 1], (int64_t)(W.negs - W.base[R - 1]))));
+    int p = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        p += L.idx[j] > i;
+#pragma unroll
+    for (int j = R - 1; j >= 1; --j) {
+        if (j > p) {
+            L.idx[j] = L.idx[j - 1];
+            L.val[j] = L.val[j - 1];
+            W.base[j] = W.base[j - 1];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (j == p) {
+            L.idx[j] = i;
+            L.val[j] = v;
+            W.base[j] = W.negs;
+        }
+    }
+}
+
+// The walk's list as a plain list (true values, drops in the bound).
+template <int R>
+__device__ __forceinline__ void tw_finish(TWalk<R> &W)
+{
+    tw_flush_drops(W);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        W.L.val[j] = W.L.idx[j] != kNoIdx
+                         ? add64(W.L.val[j], (int64_t)(W.negs - W.base[j]))
+                         : 0;
 }
 
 // One element given as its sign and radix-2^32 digits d0, d1, d2 at indices
@@ -242,20 +330,24 @@ __device__ __forceinline__ void tl_wave_merge(TList<R> &L, int lane, int width)
 // below the lowest entry of a full list (their sum is below one unit of that
 // entry); otherwise each is inserted.
 template <int R, int ND>
-__device__ __forceinline__ void tl_add_leaf(TList<R> &L, int k, uint32_t d0,
+__device__ __forceinline__ void tw_add_leaf(TWalk<R> &W, int k, uint32_t d0,
                                             uint32_t d1, uint32_t d2, bool neg)
 {
-    const int64_t sm = neg ? -1 : 0;
-    const int64_t s0 = ((int64_t)d0 ^ sm) - sm;
-    const int64_t s1 = ((int64_t)d1 ^ sm) - sm;
-    const int64_t s2 = ND == 3 ? ((int64_t)d2 ^ sm) - sm : 0;
+    const uint32_t sm = neg ? ~0u : 0u;
+    const uint32_t x0 = d0 ^ sm, x1 = d1 ^ sm, x2 = d2 ^ sm;
+    const int k1 = k + 1, k2 = k + 2;
+    W.negs += neg ? 1u : 0u;
     bool h0 = false, h1 = false, h2 = false;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const int t = L.idx[j] - k;
-        const bool e0 = t == 0, e1 = t == 1, e2 = ND == 3 && t == 2;
-        const int64_t a = e0 ? s0 : (e1 ? s1 : (e2 ? s2 : 0));
-        L.val[j] = add64(L.val[j], a);
+        const int ij = W.L.idx[j];
+        const bool e0 = ij == k, e1 = ij == k1, e2 = ND == 3 && ij == k2;
+        const uint32_t lo = e0 ? x0 : (e1 ? x1 : (e2 ? x2 : sm));
+        // val += (sm << 32) | lo as two 32-bit adds (one carry)
+        uint32_t c;
+        const uint32_t vlo = __builtin_addc((uint32_t)W.L.val[j], lo, 0u, &c);
+        const uint32_t vhi = (uint32_t)((uint64_t)W.L.val[j] >> 32) + sm + c;
+        W.L.val[j] = (int64_t)(((uint64_t)vhi << 32) | vlo);
         h0 |= e0;
         h1 |= e1;
         h2 |= e2;
@@ -264,17 +356,18 @@ __device__ __forceinline__ void tl_add_leaf(TList<R> &L, int k, uint32_t d0,
     const bool m1 = d1 != 0 && !h1;
     const bool m2 = ND == 3 && d2 != 0 && !h2;
     if (m0 || m1 || m2) {
-        const int lo = L.idx[R - 1];
-        const int top = m2 ? k + 2 : (m1 ? k + 1 : k);
+        const int lo = W.L.idx[R - 1];
+        const int top = m2 ? k2 : (m1 ? k1 : k);
         if (lo != kNoIdx && top < lo) {
-            bound_add(L.bidx, L.bval, lo, 1);
+            W.drops += 1;
         } else {
+            tw_flush_drops(W);
             if (m2)
-                tl_insert(L, k + 2, s2);
+                tw_insert(W, k2, neg ? -(int64_t)d2 : (int64_t)d2);
             if (m1)
-                tl_insert(L, k + 1, s1);
+                tw_insert(W, k1, neg ? -(int64_t)d1 : (int64_t)d1);
             if (m0)
-                tl_insert(L, k, s0);
+                tw_insert(W, k, neg ? -(int64_t)d0 : (int64_t)d0);
         }
     }
 }
@@ -283,13 +376,13 @@ __device__ __forceinline__ void tl_add_leaf(TList<R> &L, int k, uint32_t d0,
 // of 2^-1074, split at the radix-2^32 digit boundary.  Infinities and NaNs
 // set `spec` and add nothing.
 template <int R>
-__device__ __forceinline__ void leaf_f64(TList<R> &L, uint32_t lo, uint32_t hi, uint32_t &spec)
+__device__ __forceinline__ void leaf_f64(TWalk<R> &W, uint32_t lo, uint32_t hi)
 {
     const uint32_t e = (hi >> 20) & 0x7ffu;
     const bool neg = (hi >> 31) != 0;
     uint64_t m = ((uint64_t)(hi & 0xfffffu) << 32) | lo;
     if (e == 0x7ffu) {
-        spec |= special_bits(m != 0, neg);
+        W.spec |= special_bits(m != 0, neg);
         m = 0;
     } else if (e) {
         m |= 1ull << 52;
@@ -298,73 +391,73 @@ __device__ __forceinline__ void leaf_f64(TList<R> &L, uint32_t lo, uint32_t hi, 
     const int s = q & 31;
     const uint64_t w = m << s;
     const uint32_t d2 = s ? (uint32_t)(m >> (64 - s)) : 0u;
-    tl_add_leaf<R, 3>(L, q >> 5, (uint32_t)w, (uint32_t)(w >> 32), d2, neg);
+    tw_add_leaf<R, 3>(W, q >> 5, (uint32_t)w, (uint32_t)(w >> 32), d2, neg);
 }
 
 template <int R>
-__device__ __forceinline__ void leaf_f32(TList<R> &L, uint32_t b, uint32_t &spec)
+__device__ __forceinline__ void leaf_f32(TWalk<R> &W, uint32_t b)
 {
     const uint32_t e = (b >> 23) & 0xffu;
     const bool neg = (b >> 31) != 0;
     uint32_t m = b & 0x7fffffu;
     if (e == 0xffu) {
-        spec |= special_bits(m != 0, neg);
+        W.spec |= special_bits(m != 0, neg);
         m = 0;
     } else if (e) {
         m |= 1u << 23;
     }
     const int q = (e ? (int)e - 1 : 0) + 925;
     const uint64_t w = (uint64_t)m << (q & 31);
-    tl_add_leaf<R, 2>(L, q >> 5, (uint32_t)w, (uint32_t)(w >> 32), 0u, neg);
+    tw_add_leaf<R, 2>(W, q >> 5, (uint32_t)w, (uint32_t)(w >> 32), 0u, neg);
 }
 
 template <int R>
-__device__ __forceinline__ void leaf_bf16(TList<R> &L, uint32_t h, uint32_t &spec)
+__device__ __forceinline__ void leaf_bf16(TWalk<R> &W, uint32_t h)
 {
     const uint32_t e = (h >> 7) & 0xffu;
     const bool neg = ((h >> 15) & 1u) != 0;
     uint32_t m = h & 0x7fu;
     if (e == 0xffu) {
-        spec |= special_bits(m != 0, neg);
+        W.spec |= special_bits(m != 0, neg);
         m = 0;
     } else if (e) {
         m |= 1u << 7;
     }
     const int q = (e ? (int)e - 1 : 0) + 941;
     const uint64_t w = (uint64_t)m << (q & 31);
-    tl_add_leaf<R, 2>(L, q >> 5, (uint32_t)w, (uint32_t)(w >> 32), 0u, neg);
+    tw_add_leaf<R, 2>(W, q >> 5, (uint32_t)w, (uint32_t)(w >> 32), 0u, neg);
 }
 
 template <int FMT, int R>
-__device__ __forceinline__ void add_vector(TList<R> &L, const vec4u &q, uint32_t &spec)
+__device__ __forceinline__ void add_vector(TWalk<R> &W, const vec4u &q)
 {
     if constexpr (FMT == XSUM_F64) {
-        leaf_f64(L, q.x, q.y, spec);
-        leaf_f64(L, q.z, q.w, spec);
+        leaf_f64(W, q.x, q.y);
+        leaf_f64(W, q.z, q.w);
     } else if constexpr (FMT == XSUM_F32) {
-        leaf_f32(L, q.x, spec);
-        leaf_f32(L, q.y, spec);
-        leaf_f32(L, q.z, spec);
-        leaf_f32(L, q.w, spec);
+        leaf_f32(W, q.x);
+        leaf_f32(W, q.y);
+        leaf_f32(W, q.z);
+        leaf_f32(W, q.w);
     } else {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            leaf_bf16(L, q[c] & 0xffffu, spec);
-            leaf_bf16(L, q[c] >> 16, spec);
+            leaf_bf16(W, q[c] & 0xffffu);
+            leaf_bf16(W, q[c] >> 16);
         }
     }
 }
 
 template <int FMT, int R>
-__device__ __forceinline__ void add_one(TList<R> &L, const uint8_t *p, uint32_t &spec)
+__device__ __forceinline__ void add_one(TWalk<R> &W, const uint8_t *p)
 {
     if constexpr (FMT == XSUM_F64) {
         const uint32_t *w = (const uint32_t *)p;
-        leaf_f64(L, w[0], w[1], spec);
+        leaf_f64(W, w[0], w[1]);
     } else if constexpr (FMT == XSUM_F32) {
-        leaf_f32(L, *(const uint32_t *)p, spec);
+        leaf_f32(W, *(const uint32_t *)p);
     } else {
-        leaf_bf16(L, *(const uint16_t *)p, spec);
+        leaf_bf16(W, *(const uint16_t *)p);
     }
 }
 
@@ -534,9 +627,8 @@ __global__ __launch_bounds__(kTThreads) void truncated_kernel(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0)
         blk_spec = 0;
-    TList<R> L;
-    tl_clear(L);
-    uint32_t spec = 0;
+    TWalk<R> W;
+    tw_init(W);
 
     // 1. leaves: vectors tid + j*T of each tile of U*T (T threads in the grid)
     const vec4u *v = (const vec4u *)(x + (uint64_t)head * G::kBytes);
@@ -552,15 +644,18 @@ __global__ __launch_bounds__(kTThreads) void truncated_kernel(
         }
 #pragma unroll
         for (int j = 0; j < U; ++j)
-            add_vector<FMT>(L, q[j], spec);
+            add_vector<FMT>(W, q[j]);
     }
     if (blockIdx.x == 0) {
         if ((uint32_t)tid < head)
-            add_one<FMT>(L, x + (uint64_t)tid * G::kBytes, spec);
+            add_one<FMT>(W, x + (uint64_t)tid * G::kBytes);
         if ((uint32_t)tid < tail)
-            add_one<FMT>(L, x + (uint64_t)head * G::kBytes + nvec * 16 +
-                                (uint64_t)tid * G::kBytes, spec);
+            add_one<FMT>(W, x + (uint64_t)head * G::kBytes + nvec * 16 +
+                                (uint64_t)tid * G::kBytes);
     }
+    tw_finish(W);
+    TList<R> L = W.L;
+    const uint32_t spec = W.spec;
 
     // 2. tree: wave, block, grid
     tl_wave_merge(L, lane, 64);
