@@ -16,7 +16,13 @@
 // One pass, one launch:
 //   1. leaves    each lane walks its share of 16-byte vectors and adds every
 //                element's one to three radix-2^32 digits into its list,
-//                in order (the lane's share is a path of the summation tree)
+//                in order (the lane's share is a path of the summation tree).
+//                For r = 2 and 4 the list lives in registers (one compare
+//                and select per entry and digit); for r = 16 the same list
+//                lives in an LDS column with one row per digit index plus a
+//                mask of the active rows, so a digit costs one LDS add
+//                whatever r is (at one wave per SIMD, since the column takes
+//                a quarter of the LDS per wave)
 //   2. tree      lists are merged pairwise up the wave (shuffles), then the
 //                block (LDS), then the grid: each block publishes its list in
 //                the workspace and the last block to take a ticket merges
@@ -30,6 +36,7 @@
 
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "xsum.h"
 #include "xsum_device.h"
@@ -336,7 +343,7 @@ __device__ __forceinline__ void tw_add_leaf(TWalk<R> &W, int k, uint32_t d0,
     const uint32_t sm = neg ? ~0u : 0u;
     const uint32_t x0 = d0 ^ sm, x1 = d1 ^ sm, x2 = d2 ^ sm;
     const int k1 = k + 1, k2 = k + 2;
-    W.negs += neg ? 1u : 0u;
+    W.negs -= sm;  // sm is all ones for a negative element: this adds one
     bool h0 = false, h1 = false, h2 = false;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -355,47 +362,196 @@ __device__ __forceinline__ void tw_add_leaf(TWalk<R> &W, int k, uint32_t d0,
     const bool m0 = d0 != 0 && !h0;
     const bool m1 = d1 != 0 && !h1;
     const bool m2 = ND == 3 && d2 != 0 && !h2;
-    if (m0 || m1 || m2) {
-        const int lo = W.L.idx[R - 1];
-        const int top = m2 ? k2 : (m1 ? k1 : k);
-        if (lo != kNoIdx && top < lo) {
-            W.drops += 1;
-        } else {
-            tw_flush_drops(W);
-            if (m2)
-                tw_insert(W, k2, neg ? -(int64_t)d2 : (int64_t)d2);
-            if (m1)
-                tw_insert(W, k1, neg ? -(int64_t)d1 : (int64_t)d1);
-            if (m0)
-                tw_insert(W, k, neg ? -(int64_t)d0 : (int64_t)d0);
-        }
+    // the common miss (everything missing lies below a full list) is counted
+    // without a branch; only insertions branch
+    const bool miss = m0 || m1 || m2;
+    const int lo = W.L.idx[R - 1];
+    const int top = m2 ? k2 : (m1 ? k1 : k);
+    const bool drop = lo != kNoIdx && top < lo;
+    W.drops += (miss && drop) ? 1u : 0u;
+    if (miss && !drop) {
+        tw_flush_drops(W);
+        if (m2)
+            tw_insert(W, k2, neg ? -(int64_t)d2 : (int64_t)d2);
+        if (m1)
+            tw_insert(W, k1, neg ? -(int64_t)d1 : (int64_t)d1);
+        if (m0)
+            tw_insert(W, k, neg ? -(int64_t)d0 : (int64_t)d0);
     }
 }
+
+template <int R>
+struct RegWalk : TWalk<R> {
+    template <int ND>
+    __device__ __forceinline__ void add_leaf(int k, uint32_t d0, uint32_t d1, uint32_t d2, bool neg)
+    {
+        tw_add_leaf<R, ND>(*this, k, d0, d1, d2, neg);
+    }
+    __device__ __forceinline__ void finish(TList<R> &out)
+    {
+        tw_finish(*this);
+        out = this->L;
+    }
+};
+
+// A lane's list kept as a column of radix-2^32 rows in LDS (row i at
+// col[i * kTThreads]) plus a mask of the active rows: the same list, with
+// the entries' values at their index's row, so a digit whose index is active
+// is one LDS add at its row whatever r is.  Inactive rows are zero.
+constexpr int kRows = 66;
+
+template <int R>
+struct ColWalk {
+    uint64_t *col;
+    uint64_t act;     // active rows 0..63
+    uint32_t acth;    // active rows 64, 65
+    int cnt, lo;      // active rows; the lowest one when cnt == R
+    int bidx;
+    uint64_t bval;
+    uint32_t drops, spec;
+
+    __device__ __forceinline__ void init(uint64_t *c)
+    {
+        col = c;
+        act = 0;
+        acth = 0;
+        cnt = 0;
+        lo = kNoIdx;
+        bidx = 0;
+        bval = 0;
+        drops = 0;
+        spec = 0;
+#pragma unroll
+        for (int i = 0; i < kRows; ++i)
+            lds_store(col + i * kTThreads, 0ull);
+    }
+    __device__ __forceinline__ void set_bit(int i)
+    {
+        if (i < 64)
+            act |= 1ull << i;
+        else
+            acth |= 1u << (i - 64);
+    }
+    __device__ __forceinline__ void clear_bit(int i)
+    {
+        if (i < 64)
+            act &= ~(1ull << i);
+        else
+            acth &= ~(1u << (i - 64));
+    }
+    __device__ __forceinline__ int lowest() const
+    {
+        return act ? __builtin_ctzll(act) : 64 + __builtin_ctz(acth);
+    }
+    __device__ __forceinline__ int highest() const
+    {
+        return acth ? 95 - __builtin_clz(acth) : (act ? 63 - __builtin_clzll(act) : kNoIdx);
+    }
+    __device__ __forceinline__ void flush()
+    {
+        if (drops) {
+            bound_add(bidx, bval, lo, drops);
+            drops = 0;
+        }
+    }
+    // (i, v) for an inactive row i (which holds zero)
+    __device__ __forceinline__ void insert(int i, int64_t v)
+    {
+        if (cnt == R && i < lo) {
+            bound_add(bidx, bval, i, mag64(v));
+            return;
+        }
+        if (cnt == R) {
+            uint64_t *pl = col + lo * kTThreads;
+            const int64_t ev = (int64_t)lds_load(pl);
+            lds_store(pl, 0ull);
+            clear_bit(lo);
+            --cnt;
+            bound_add(bidx, bval, lo, mag64(ev));
+        }
+        lds_store(col + i * kTThreads, (uint64_t)v);
+        set_bit(i);
+        ++cnt;
+        if (cnt == R)
+            lo = lowest();
+    }
+    template <int ND>
+    __device__ __forceinline__ void add_leaf(int k, uint32_t d0, uint32_t d1, uint32_t d2, bool neg)
+    {
+        // rows k..k+2 (k <= 63): the low word shifted down, rows 64 and 65
+        // from the high word shifted into place
+        const uint32_t on = ((uint32_t)(act >> k) |
+                             (k >= 62 ? acth << (64 - k) : 0u)) & 7u;
+        const uint32_t nz = (d0 != 0 ? 1u : 0u) | (d1 != 0 ? 2u : 0u) |
+                            (ND == 3 && d2 != 0 ? 4u : 0u);
+        const int64_t sm = neg ? -1 : 0;
+        const int64_t s0 = ((int64_t)d0 ^ sm) - sm;
+        const int64_t s1 = ((int64_t)d1 ^ sm) - sm;
+        const int64_t s2 = ND == 3 ? ((int64_t)d2 ^ sm) - sm : 0;
+        uint64_t *p = col + k * kTThreads;
+        const uint32_t hit = nz & on;
+        if (hit & 1u)
+            lds_add(p, (uint64_t)s0);
+        if (hit & 2u)
+            lds_add(p + kTThreads, (uint64_t)s1);
+        if (ND == 3 && (hit & 4u))
+            lds_add(p + 2 * kTThreads, (uint64_t)s2);
+        const uint32_t miss = nz & ~on;
+        const int top = k + 31 - __builtin_clz(miss | 1u);
+        const bool drop = cnt == R && top < lo;
+        drops += (miss && drop) ? 1u : 0u;
+        if (miss && !drop) {
+            flush();
+#pragma unroll 1
+            for (int c = 2; c >= 0; --c)
+                if ((miss >> c) & 1u)
+                    insert(k + c, c == 2 ? s2 : (c == 1 ? s1 : s0));
+        }
+    }
+    __device__ __forceinline__ void finish(TList<R> &out)
+    {
+        flush();
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int h = highest();
+            if (h != kNoIdx) {
+                uint64_t *ph = col + h * kTThreads;
+                out.idx[j] = h;
+                out.val[j] = (int64_t)lds_load(ph);
+                lds_store(ph, 0ull);
+                clear_bit(h);
+            } else {
+                out.idx[j] = kNoIdx;
+                out.val[j] = 0;
+            }
+        }
+        out.bidx = bidx;
+        out.bval = bval;
+    }
+};
 
 // Element decoders: exponent position q of the significand's bit 0 in units
 // of 2^-1074, split at the radix-2^32 digit boundary.  Infinities and NaNs
 // set `spec` and add nothing.
-template <int R>
-__device__ __forceinline__ void leaf_f64(TWalk<R> &W, uint32_t lo, uint32_t hi)
+template <typename WT>
+__device__ __forceinline__ void leaf_f64(WT &W, uint32_t lo, uint32_t hi)
 {
     const uint32_t e = (hi >> 20) & 0x7ffu;
     const bool neg = (hi >> 31) != 0;
-    uint64_t m = ((uint64_t)(hi & 0xfffffu) << 32) | lo;
-    if (e == 0x7ffu) {
-        W.spec |= special_bits(m != 0, neg);
-        m = 0;
-    } else if (e) {
-        m |= 1ull << 52;
-    }
+    const bool special = e == 0x7ffu;
+    if (special)
+        W.spec |= special_bits(((hi & 0xfffffu) | lo) != 0, neg);
+    const uint32_t mh = special ? 0u : ((hi & 0xfffffu) | (e ? 0x100000u : 0u));
+    const uint64_t m = ((uint64_t)mh << 32) | (special ? 0u : lo);
     const int q = e ? (int)e - 1 : 0;
     const int s = q & 31;
     const uint64_t w = m << s;
     const uint32_t d2 = s ? (uint32_t)(m >> (64 - s)) : 0u;
-    tw_add_leaf<R, 3>(W, q >> 5, (uint32_t)w, (uint32_t)(w >> 32), d2, neg);
+    W.template add_leaf<3>(q >> 5, (uint32_t)w, (uint32_t)(w >> 32), d2, neg);
 }
 
-template <int R>
-__device__ __forceinline__ void leaf_f32(TWalk<R> &W, uint32_t b)
+template <typename WT>
+__device__ __forceinline__ void leaf_f32(WT &W, uint32_t b)
 {
     const uint32_t e = (b >> 23) & 0xffu;
     const bool neg = (b >> 31) != 0;
@@ -408,11 +564,11 @@ __device__ __forceinline__ void leaf_f32(TWalk<R> &W, uint32_t b)
     }
     const int q = (e ? (int)e - 1 : 0) + 925;
     const uint64_t w = (uint64_t)m << (q & 31);
-    tw_add_leaf<R, 2>(W, q >> 5, (uint32_t)w, (uint32_t)(w >> 32), 0u, neg);
+    W.template add_leaf<2>(q >> 5, (uint32_t)w, (uint32_t)(w >> 32), 0u, neg);
 }
 
-template <int R>
-__device__ __forceinline__ void leaf_bf16(TWalk<R> &W, uint32_t h)
+template <typename WT>
+__device__ __forceinline__ void leaf_bf16(WT &W, uint32_t h)
 {
     const uint32_t e = (h >> 7) & 0xffu;
     const bool neg = ((h >> 15) & 1u) != 0;
@@ -425,11 +581,11 @@ __device__ __forceinline__ void leaf_bf16(TWalk<R> &W, uint32_t h)
     }
     const int q = (e ? (int)e - 1 : 0) + 941;
     const uint64_t w = (uint64_t)m << (q & 31);
-    tw_add_leaf<R, 2>(W, q >> 5, (uint32_t)w, (uint32_t)(w >> 32), 0u, neg);
+    W.template add_leaf<2>(q >> 5, (uint32_t)w, (uint32_t)(w >> 32), 0u, neg);
 }
 
-template <int FMT, int R>
-__device__ __forceinline__ void add_vector(TWalk<R> &W, const vec4u &q)
+template <int FMT, typename WT>
+__device__ __forceinline__ void add_vector(WT &W, const vec4u &q)
 {
     if constexpr (FMT == XSUM_F64) {
         leaf_f64(W, q.x, q.y);
@@ -448,8 +604,8 @@ __device__ __forceinline__ void add_vector(TWalk<R> &W, const vec4u &q)
     }
 }
 
-template <int FMT, int R>
-__device__ __forceinline__ void add_one(TWalk<R> &W, const uint8_t *p)
+template <int FMT, typename WT>
+__device__ __forceinline__ void add_one(WT &W, const uint8_t *p)
 {
     if constexpr (FMT == XSUM_F64) {
         const uint32_t *w = (const uint32_t *)p;
@@ -615,7 +771,7 @@ __device__ __forceinline__ void finish_root(const TList<R> &L, uint32_t spec, in
     }
 }
 
-template <int FMT, int R, int U>
+template <int FMT, int R, int U, bool COL>
 __global__ __launch_bounds__(kTThreads) void truncated_kernel(
     const uint8_t *__restrict__ x, uint32_t head, uint64_t nvec, uint32_t tail,
     TCtl *ctl, TNode *nodes, xsum_trunc_root_t *rec, int out_fmt)
@@ -627,8 +783,12 @@ __global__ __launch_bounds__(kTThreads) void truncated_kernel(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0)
         blk_spec = 0;
-    TWalk<R> W;
-    tw_init(W);
+    __shared__ uint64_t cols[COL ? kRows : 1][kTThreads];
+    std::conditional_t<COL, ColWalk<R>, RegWalk<R>> W;
+    if constexpr (COL)
+        W.init(&cols[0][tid]);
+    else
+        tw_init(W);
 
     // 1. leaves: vectors tid + j*T of each tile of U*T (T threads in the grid)
     const vec4u *v = (const vec4u *)(x + (uint64_t)head * G::kBytes);
@@ -642,7 +802,7 @@ __global__ __launch_bounds__(kTThreads) void truncated_kernel(
             if (i < nvec)
                 q[j] = __builtin_nontemporal_load(v + i);
         }
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int j = 0; j < U; ++j)
             add_vector<FMT>(W, q[j]);
     }
@@ -653,8 +813,8 @@ __global__ __launch_bounds__(kTThreads) void truncated_kernel(
             add_one<FMT>(W, x + (uint64_t)head * G::kBytes + nvec * 16 +
                                 (uint64_t)tid * G::kBytes);
     }
-    tw_finish(W);
-    TList<R> L = W.L;
+    TList<R> L;
+    W.finish(L);
     const uint32_t spec = W.spec;
 
     // 2. tree: wave, block, grid
@@ -728,7 +888,10 @@ template <int FMT, int R>
 hipError_t launch_round_fmt(const void *x, uint64_t n, TCtl *ctl, TNode *nodes,
                             xsum_trunc_root_t *rec, int out_fmt, int cus, hipStream_t s)
 {
-    constexpr int U = R <= 4 ? 8 : 4;
+    // r = 16: the LDS column (one add per digit whatever r is); r = 2 and
+    // 4: the register list (more waves per SIMD, fewer entries to compare)
+    constexpr bool COL = R > 4;
+    constexpr int U = 8;
     using G = Geo<FMT>;
     const uintptr_t addr = (uintptr_t)x;
     uint64_t head = addr % 16 ? (16 - addr % 16) / G::kBytes : 0;
@@ -739,14 +902,14 @@ hipError_t launch_round_fmt(const void *x, uint64_t n, TCtl *ctl, TNode *nodes,
     const uint32_t tail = (uint32_t)((body % 16) / G::kBytes);
     const uint64_t per_block = (uint64_t)kTThreads * U;
     uint64_t blocks = (nvec + per_block - 1) / per_block;
-    const uint64_t cap = (uint64_t)cus * 4;
+    const uint64_t cap = (uint64_t)cus * (COL ? 1 : 4);
     if (blocks > cap)
         blocks = cap;
     if (blocks > (uint64_t)kMaxTBlocks)
         blocks = kMaxTBlocks;
     if (blocks < 1)
         blocks = 1;
-    hipLaunchKernelGGL((truncated_kernel<FMT, R, U>), dim3((unsigned)blocks), dim3(kTThreads),
+    hipLaunchKernelGGL((truncated_kernel<FMT, R, U, COL>), dim3((unsigned)blocks), dim3(kTThreads),
                        0, s, (const uint8_t *)x, (uint32_t)head, nvec, tail, ctl, nodes, rec,
                        out_fmt);
     return hipGetLastError();

@@ -12,6 +12,9 @@ benchmark times (the library's persistent default grid).
   bfloat16 sum runs the 32-bit column entries with their periodic flushes.
 * 10^6 segments of config 4 from one captured graph: every segment equals
   the oracle's; all 10^6 results are identical across replays and plans.
+* Section 4's truncated iteration on the 2^28 and 2^31 binary64 inputs:
+  the same bits and flags as the oracle, and every pass (r = 2, 4, 16)
+  within its bound of the oracle's exact integer.
 """
 
 import gc
@@ -46,6 +49,33 @@ def _release():
     torch.cuda.empty_cache()
 
 
+def _check_truncated(x, n, acc, want):
+    """Section 4's iteration equals the exact rounding; every pass's root is
+    within its bound of the exact integer, and a certified pass carries the
+    exact rounding."""
+    import torch
+    import paper_1605_05436_amd as xs
+    wsb = xs.xsum_truncated_workspace_size()
+    ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda")
+    got = xs.xsum_exact_sum_truncated(x.data_ptr(), n, xs.F64, xs.F64, ws.data_ptr(), wsb,
+                                      xs.stream_handle())
+    assert got[:2] == want and got[2] in (2, 4, 16, 0)
+    rec = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    for r in (2, 4, 16):
+        print("truncated pass r=%d n=%d" % (r, n), flush=True)
+        xs.xsum_truncated_round(x.data_ptr(), n, xs.F64, xs.F64, r, rec.data_ptr(),
+                                ws.data_ptr(), wsb, xs.stream_handle())
+        torch.cuda.synchronize()
+        root = xs.read_trunc_root(rec)
+        s = sum(root.value[j] << (32 * root.index[j]) for j in range(root.count))
+        bound = root.bound_value << (32 * root.bound_index) if root.bound_value else 0
+        assert root.count <= r
+        if not root.special:
+            assert abs(acc.total - s) <= bound
+        if root.certified:
+            assert (root.bits, root.flags) == want
+
+
 @pytest.mark.parametrize("variant", ["a", "b"])
 def test_config2_full_size(variant):
     print("config2 variant", variant, "n=2^28", flush=True)
@@ -56,6 +86,7 @@ def test_config2_full_size(variant):
     got = gpu_sum_async(x, len(bits), "f64")
     assert got[:2] == tuple(oracle.finish(acc, "f64"))
     assert got[2] == bytes(576)
+    _check_truncated(x, len(bits), acc, tuple(oracle.finish(acc, "f64")))
     del x
     _release()
 
@@ -69,6 +100,7 @@ def test_config3_full_size_balanced():
     del bits
     got = gpu_sum_async(x, n, "f64")
     assert got[:2] == tuple(oracle.finish(acc, "f64"))
+    _check_truncated(x, n, acc, tuple(oracle.finish(acc, "f64")))
     del x
     _release()
 
