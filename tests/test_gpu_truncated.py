@@ -10,7 +10,9 @@ certified pass carries the exact rounding.  Which pass certifies depends on
 the tree's shape, which differs from the oracle's balanced tree, so it is
 only checked where it is forced: no truncation at all (r = 2 certifies), or
 more active indices above the only non-cancelling term than r = 16 keeps
-(only the untruncated pass is exact)."""
+(only the untruncated pass is exact).  The r = 2 and 4 passes keep their
+lists in registers and the r = 16 pass in LDS columns, so every test runs
+all three passes."""
 
 import numpy as np
 import pytest
@@ -154,10 +156,12 @@ def test_empty_zero_and_specials(ws):
         t = to_device(bits)
         got = run_blocking(t, len(bits), "f64", ws)
         assert got[:2] == want, vals
-        for r in (2, 4):
+        for r in (2, 4, 16):
             rec = run_pass(t, len(bits), "f64", r, ws)
             if any(not math.isfinite(v) for v in vals):
                 assert rec.certified and (rec.bits, rec.flags) == want
+            else:
+                check_pass(rec, r, oracle.exact_sum(bits, "f64").total, want)
 
 
 def test_pass_count_where_it_is_forced(ws):
