@@ -12,9 +12,10 @@ benchmark times (the library's persistent default grid).
   bfloat16 sum runs the 32-bit column entries with their periodic flushes.
 * 10^6 segments of config 4 from one captured graph: every segment equals
   the oracle's; all 10^6 results are identical across replays and plans.
-* Section 4's truncated iteration on the 2^28 and 2^31 binary64 inputs:
-  the same bits and flags as the oracle, and every pass (r = 2, 4, 16)
-  within its bound of the oracle's exact integer.
+* Section 4's truncated iteration on the 2^28 and 2^31 binary64 inputs and
+  the 2 GiB binary32 and bfloat16 ones: the same bits and flags as the
+  oracle, and every pass (r = 2, 4, 16) within its bound of the oracle's
+  exact integer.
 """
 
 import gc
@@ -49,21 +50,22 @@ def _release():
     torch.cuda.empty_cache()
 
 
-def _check_truncated(x, n, acc, want):
+def _check_truncated(x, n, acc, want, fmt="f64"):
     """Section 4's iteration equals the exact rounding; every pass's root is
     within its bound of the exact integer, and a certified pass carries the
     exact rounding."""
     import torch
     import paper_1605_05436_amd as xs
+    code = {"f64": xs.F64, "f32": xs.F32, "bf16": xs.BF16}[fmt]
     wsb = xs.xsum_truncated_workspace_size()
     ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda")
-    got = xs.xsum_exact_sum_truncated(x.data_ptr(), n, xs.F64, xs.F64, ws.data_ptr(), wsb,
+    got = xs.xsum_exact_sum_truncated(x.data_ptr(), n, code, xs.SAME, ws.data_ptr(), wsb,
                                       xs.stream_handle())
     assert got[:2] == want and got[2] in (2, 4, 16, 0)
     rec = torch.zeros(256, dtype=torch.uint8, device="cuda")
     for r in (2, 4, 16):
         print("truncated pass r=%d n=%d" % (r, n), flush=True)
-        xs.xsum_truncated_round(x.data_ptr(), n, xs.F64, xs.F64, r, rec.data_ptr(),
+        xs.xsum_truncated_round(x.data_ptr(), n, code, xs.SAME, r, rec.data_ptr(),
                                 ws.data_ptr(), wsb, xs.stream_handle())
         torch.cuda.synchronize()
         root = xs.read_trunc_root(rec)
@@ -118,6 +120,7 @@ def test_config3_full_size_overflow_state():
     want = tuple(oracle.finish(acc, "f64"))
     assert got[:2] == want
     assert want[1] & oracle.FLAG_OVERFLOW
+    _check_truncated(x, n, acc, want)
     st = xs.new_states(1)
     xs.xsum_acc_add(st.data_ptr(), x.data_ptr(), n, xs.F64, xs.stream_handle())
     torch.cuda.synchronize()
@@ -151,6 +154,7 @@ def test_narrow_formats_full_size(fmt):
     got = gpu_sum_async(x, n, fmt, blocks=3)
     assert got[:2] == want
     assert got[2] == bytes(576)
+    _check_truncated(x, n, acc, want, fmt)
     del x
     _release()
 
