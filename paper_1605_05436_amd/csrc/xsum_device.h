@@ -640,76 +640,6 @@ static __device__ __forceinline__ uint64_t round_wave(int64_t a, int64_t b, int 
     return round_magnitude(neg, h, w[0], w[1], w[2], sticky, f, flags);
 }
 
-
-// ------------------------------------------------- per-lane rounding --
-//
-// A lane that summed a whole segment in its own column rounds it alone, with
-// no help from other lanes: a sequential scan carries the signed digits
-// upward (Section 5, step 4: a scan that propagates the signed carries) and
-// the most significant non-zero digits are rounded (step 5).
-
-// Two-pass rounding of one lane's digits (digit d of the lane is at
-// col[d * 64], weight 2^(32 (digit0 + d)) in units of 2^-1074), used when a
-// lane owns a whole segment.  Pass 1 carries the N raw digits upward and
-// writes the canonical digits back, noting the lowest non-zero digit z, the
-// highest non-zero digit and the highest digit that is not all ones; the
-// final carry is the sign.  Pass 2 reads the three digits the rounding needs:
-// for a negative sum the magnitude's digits are 0 below z, 2^32 - u at z and
-// 2^32 - 1 - u above it, so in both cases "any non-zero digit below h - 2"
-// is simply z < h - 2.  The N entries are zeroed afterwards.
-template <int N>
-__device__ __forceinline__ uint64_t finish_lane_digits(uint64_t *col,
-                                                       int digit0,
-                                                       uint32_t special,
-                                                       int out_fmt,
-                                                       uint32_t &flags)
-{
-    int64_t carry = 0;
-    int z = -1, hnz = -1, hff = -1;
-#pragma unroll
-    for (int d = 0; d < N; ++d) {
-        const int64_t x = (int64_t)lds_load(col + d * 64) + carry;
-        const uint32_t u = (uint32_t)((uint64_t)x & kLow32);
-        carry = x >> 32;
-        lds_store(col + d * 64, u);
-        if (u != 0) {
-            hnz = d;
-            z = (z < 0) ? d : z;
-        }
-        if (u != 0xffffffffu)
-            hff = d;
-    }
-    const OutFormat f = out_format(out_fmt);
-    flags = 0;
-    uint64_t bits;
-    const bool negative = carry < 0;
-    if (special_result(special, f, bits, flags)) {
-    } else if (!(carry == 0 || carry == -1) || (negative && z < 0)) {
-        // beyond the digits: far above every format's range
-        flags = XSUM_FLAG_OVERFLOW | XSUM_FLAG_INEXACT;
-        bits = fmt_inf(f, negative);
-    } else if (!negative && hnz < 0) {
-        bits = 0;                                   // exact zero -> +0
-    } else {
-        const int h = negative ? (hff > z ? hff : z) : hnz;
-        uint32_t w[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const int d = h - i;
-            uint32_t u = d >= 0 ? (uint32_t)lds_load(col + (d >= 0 ? d : 0) * 64) : 0u;
-            if (negative)
-                u = d < z ? 0u : (d == z ? 0u - u : ~u);
-            w[i] = u;
-        }
-        bits = round_magnitude(negative, digit0 + h, w[0], w[1], w[2], z < h - 2,
-                               f, flags);
-    }
-#pragma unroll
-    for (int d = 0; d < N; ++d)
-        lds_store(col + d * 64, 0);
-    return bits;
-}
-
 __device__ __forceinline__ void store_result(void *out, int out_fmt,
                                              uint64_t bits)
 {
