@@ -63,10 +63,6 @@ def run_pass(t, n, fmt, r, ws, out_fmt=None):
     return xs.read_trunc_root(rec)
 
 
-def out_of(fmt, out_fmt):
-    return out_fmt or ("f32" if fmt == "bf16" else fmt)
-
-
 def check_pass(rec, r, exact_total, want):
     """What every correct pass satisfies, whatever its tree."""
     assert rec.r == r and rec.count <= r
