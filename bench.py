@@ -167,6 +167,13 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="segmented workload: use the library's default tuning")
+    ap.add_argument("--clock-trace", type=int, default=0, metavar="LAUNCHES",
+                    help="single workloads: after an idle pause, time LAUNCHES "
+                         "back-to-back launches one by one while a one-wave "
+                         "kernel on a second stream samples the shader clock")
+    ap.add_argument("--seg-lanes", type=int, default=0, choices=[0, 1, 2, 4, 8, 16],
+                    help="segmented workload: give every lane-group segment "
+                         "this many lanes (no autotuning); 0 = tuned")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run one device copy of the input "
                          "(a plain copy kernel of known size, for scaling "
@@ -225,6 +232,70 @@ def cold_median_ms(step, stream, flush_buf, reps=20):
         times.append(e0.elapsed_time(e1))
     times.sort()
     return times[len(times) // 2]
+
+
+def clock_trace(step, stream, launches, est_ms, idle_s=3.0, interval_ticks=5000):
+    """Per-launch times of `launches` back-to-back launches from an idle GPU,
+    with the shader clock sampled every interval_ticks of the 100 MHz
+    counter (50 us by default) by xsum_probe_clock on a second stream.
+    Returns launch-time means over ranges of launches, the clock per 5 ms of
+    the run, and the clock before the first launch."""
+    import torch
+    import paper_1605_05436_amd as xs
+    torch.cuda.synchronize()
+    time.sleep(idle_s)
+    sh = xs.stream_handle(stream)
+    side = torch.cuda.Stream()
+    # sample from 5 ms before the first launch until well past the last
+    # (est_ms: the launch time measured before; at most 10 s)
+    span_us = 5000.0 + 2.0 * launches * est_ms * 1e3 + 50_000.0
+    nsamp = int(min(200_000, span_us * 100.0 / interval_ticks))
+    samples = torch.zeros(2 * nsamp, dtype=torch.int64, device="cuda")
+    marks = torch.zeros(4, dtype=torch.int64, device="cuda")
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(launches + 1)]
+    xs.xsum_probe_clock(samples.data_ptr(), nsamp, interval_ticks, xs.stream_handle(side))
+    time.sleep(0.005)           # a few idle samples first
+    xs.xsum_probe_clock(marks.data_ptr(), 1, 1, sh)
+    for i in range(launches):
+        evs[i].record(stream)
+        step()
+    evs[launches].record(stream)
+    xs.xsum_probe_clock(marks[2:].data_ptr(), 1, 1, sh)
+    torch.cuda.synchronize()
+    d = np.array([evs[i].elapsed_time(evs[i + 1]) * 1e3 for i in range(launches)])
+    s = samples.cpu().numpy().reshape(-1, 2).astype(np.float64)
+    m = marks.cpu().numpy().astype(np.float64)
+    rt, ck = s[:, 0], s[:, 1]
+    mhz = np.diff(ck) / np.diff(rt) * 100.0
+    t_us = (rt[1:] - m[0]) / 100.0                 # since the first launch
+    end_us = (m[2] - m[0]) / 100.0
+    ranges = {}
+    for a, b in ((0, 5), (5, 25), (25, 50), (50, 100), (100, 200), (200, 400),
+                 (400, launches)):
+        if a < min(b, launches):
+            seg = d[a:b]
+            ranges["%d-%d" % (a + 1, min(b, launches))] = [
+                round(float(seg.mean()), 1), round(float(seg.min()), 1),
+                round(float(seg.max()), 1)]
+    buckets = []
+    for b0 in np.arange(0.0, end_us, 5000.0):
+        sel = (t_us >= b0) & (t_us < b0 + 5000.0)
+        if sel.any():
+            buckets.append([round(b0 / 1e3, 1), round(float(mhz[sel].mean())),
+                            round(float(mhz[sel].min()))])
+    before = mhz[t_us < 0]
+    out = {"launches": launches, "span_ms": round(end_us / 1e3, 2),
+           "launch_us_mean_min_max": ranges,
+           "clock_mhz_per_5ms": buckets,
+           "clock_mhz_before": round(float(before.mean())) if len(before) else None,
+           "first_launches_us": [round(float(v), 1) for v in d[:30]]}
+    log("clock trace: %d launches over %.1f ms, clock before %s MHz"
+        % (launches, end_us / 1e3, out["clock_mhz_before"]))
+    for k, v in ranges.items():
+        log("  launches %-9s mean %.1f us (min %.1f, max %.1f)" % (k, *v))
+    for t0, c, cmin in buckets:
+        log("  t %6.1f ms: clock %d MHz (min %d)" % (t0, c, cmin))
+    return out
 
 
 def bench_single(args):
@@ -327,6 +398,13 @@ def bench_single(args):
         exact_val = float(struct.unpack("<f", struct.pack("<I", want_bits))[0])
     log("oracle: %.3f s per run (median of %d) on %d threads, bit_exact=%s"
         % (cpu_s, cpu_runs, threads, bit_exact))
+    trace = (clock_trace(step, stream, args.clock_trace, ms_per_step)
+             if args.clock_trace else None)
+    if trace is not None:
+        # the traced launches wrote the same result
+        trace["same_result"] = (int(out.cpu().numpy().view(np.uint64)[0]) &
+                                ((1 << (8 * (8 if out_fmt == "f64" else 4))) - 1),
+                                int(flags.cpu()[0])) == (result_bits, result_flags)
 
     achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
     metric = ("exact FP64 sum Gelem/s + % HBM roofline vs torch.sum on same GPU (bit-exact)"
@@ -357,6 +435,8 @@ def bench_single(args):
     }
     if probe:
         rec["measured_peak"] = probe
+    if trace is not None:
+        rec["clock_trace"] = trace
 
     if not args.no_torch_sum:
         xf = x.view({"f64": torch.float64, "f32": torch.float32,
@@ -610,7 +690,14 @@ def bench_segmented(args):
     # and vectors in flight per format and size bucket
     from paper_1605_05436_amd import autotune
     t0 = time.time()
-    if args.no_autotune:
+    if args.seg_lanes:
+        # every lane-group segment gets the same number of lanes
+        g = args.seg_lanes
+        best = autotune._full(autotune.DEFAULT_CANDIDATES[0])[:7] + \
+            (tuple(tuple(g for _ in range(autotune.NB)) for _ in range(3)),
+             autotune.EMPTY_TABLE)
+        table = []
+    elif args.no_autotune:
         best, table = autotune._full(autotune.DEFAULT_CANDIDATES[0]), []
     else:
         best, table = autotune.tune_segmented(desc, dbuf, use_cache=False)
@@ -673,7 +760,8 @@ def bench_segmented(args):
            "config": {"workload": "1e6 segments, lognormal lengths (median 256, sigma 2, "
                                   "clip [1, 2^20]), f64/f32/bf16 50/37.5/12.5, one graph launch",
                       "segments": len(desc), "elements": nel, "bytes": nbytes,
-                      "seed": args.seed},
+                      "seed": args.seed,
+                      "lanes_per_segment": args.seg_lanes or "planner/autotuner"},
            "bit_exact": ok, "checked_segments": int(len(desc)),
            "cpu_baseline": {"value": round(nel / cpu_s / 1e9, 4), "unit": "Gelem/s",
                             "cores": cpu_threads, "kind": "oracle",

@@ -35,6 +35,24 @@ xsum_status_t xsum_probe_read(const void *x, uint64_t nbytes, uint32_t *sink, vo
  */
 xsum_status_t xsum_probe_flush(void *buf, uint64_t nbytes, uint32_t value, void *stream);
 
+/*
+ * Sample the shader clock while other work runs: one single-wave kernel on
+ * `stream` takes nsamples samples, one every interval_ticks ticks of the
+ * GPU's 100 MHz constant-rate counter, and writes for sample i
+ *   out[2i]     the constant-rate counter (100 MHz ticks)
+ *   out[2i + 1] the shader-clock counter of the compute unit it runs on,
+ * so the shader clock over a sample interval is
+ *   (out[2i+3] - out[2i+1]) / (out[2i+2] - out[2i]) * 100 MHz.
+ * Launched on a stream of its own before a run of timed launches on another
+ * stream, it shows how the clock moves under that load.  The kernel runs for
+ * nsamples * interval_ticks / 100 MHz whatever else the GPU does.
+ *   out     device, 16 * nsamples bytes, 8-byte aligned
+ * XSUM_ERANGE unless nsamples <= 2^20, interval_ticks >= 1 and
+ * nsamples * interval_ticks <= 10^9 (10 s); nsamples = 0 is a no-op.
+ */
+xsum_status_t xsum_probe_clock(uint64_t *out, uint32_t nsamples, uint32_t interval_ticks,
+                               void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,7 +37,7 @@ EXPORTED = [
     "xsum_exact_sum_segmented", "xsum_segmented_workspace_init",
     "xsum_segmented_run", "xsum_segmented_run_noalloc", "xsum_segmented_capture", "xsum_graph_launch",
     "xsum_graph_destroy", "xsum_batch_item_tasks", "xsum_batch_add",
-    "xsum_batch_finalize", "xsum_probe_read", "xsum_probe_flush",
+    "xsum_batch_finalize", "xsum_probe_read", "xsum_probe_flush", "xsum_probe_clock",
     "xsum_truncated_workspace_size", "xsum_truncated_round",
     "xsum_exact_sum_truncated",
 ]
@@ -190,6 +190,8 @@ def _load():
     lib.xsum_probe_read.argtypes = [vp, u64, vp, vp]
     lib.xsum_probe_flush.restype = i32
     lib.xsum_probe_flush.argtypes = [vp, u64, ctypes.c_uint32, vp]
+    lib.xsum_probe_clock.restype = i32
+    lib.xsum_probe_clock.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp]
     lib.xsum_truncated_workspace_size.restype = ctypes.c_size_t
     lib.xsum_truncated_workspace_size.argtypes = []
     lib.xsum_truncated_round.restype = i32
@@ -420,6 +422,12 @@ def xsum_probe_read(x, nbytes, sink, stream=0):
 def xsum_probe_flush(buf, nbytes, value=0, stream=0):
     """Measurement only: fill nbytes at buf with a 32-bit value."""
     _check(_lib.xsum_probe_flush(_p(buf), nbytes, value, _p(stream)))
+
+
+def xsum_probe_clock(out, nsamples, interval_ticks, stream=0):
+    """Measurement only: sample (100 MHz counter, shader clock counter)
+    nsamples times, every interval_ticks ticks, into out[2i], out[2i+1]."""
+    _check(_lib.xsum_probe_clock(_p(out), nsamples, interval_ticks, _p(stream)))
 
 
 # ----------------------------------------------------- torch marshalling --

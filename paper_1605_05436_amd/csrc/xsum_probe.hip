@@ -1,7 +1,8 @@
 // Measurement kernels that carry none of the method: a plain streaming read
 // with the launch shape of the binary64 single-sum kernel (the practical
-// read ceiling that kernel is compared with) and a buffer fill used to evict
-// a working set from the caches between timed runs.
+// read ceiling that kernel is compared with), a buffer fill used to evict
+// a working set from the caches between timed runs, and a sampler of the
+// shader clock against the constant-rate clock, run beside timed launches.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -21,6 +22,9 @@ namespace {
 typedef uint32_t vec4u __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 2, kUnroll = 16, kBlocksPerCu = 2;
+// the clock sampler runs for at most 10 s of the 100 MHz counter
+constexpr uint32_t kClockMaxSamples = 1u << 20;
+constexpr uint64_t kClockMaxTicks = 1000000000ull;
 
 // Every wave streams its own run of 64 * kUnroll 16-byte vectors per tile
 // with non-temporal loads, the next tile in flight while the current one is
@@ -90,6 +94,27 @@ __global__ void fill_kernel(uint32_t *p, uint64_t words, uint32_t value)
         p[i] = value;
 }
 
+// One lane takes nsamples samples, one every `interval` ticks of the
+// 100 MHz constant-rate counter: that counter and the shader-clock counter,
+// read back to back.  Every wait ends when the constant-rate counter passes
+// its target, so the kernel runs for nsamples * interval ticks.
+__global__ __launch_bounds__(64) void clock_probe_kernel(uint64_t *out, uint32_t nsamples,
+                                                         uint32_t interval)
+{
+    if (threadIdx.x != 0)
+        return;
+    const uint64_t t0 = wall_clock64();
+    for (uint32_t i = 0; i < nsamples; ++i) {
+        const uint64_t target = t0 + (uint64_t)(i + 1) * interval;
+        while (wall_clock64() < target) {
+        }
+        const uint64_t rt = wall_clock64();
+        const uint64_t ck = clock64();
+        out[2 * (uint64_t)i] = rt;
+        out[2 * (uint64_t)i + 1] = ck;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -130,6 +155,23 @@ xsum_status_t xsum_probe_flush(void *buf, uint64_t nbytes, uint32_t value, void 
         blocks = 4096;
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0,
                        (hipStream_t)stream, (uint32_t *)buf, words, value);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? XSUM_OK : xsum::api_hip_fail(e, "kernel launch");
+}
+
+xsum_status_t xsum_probe_clock(uint64_t *out, uint32_t nsamples, uint32_t interval_ticks,
+                               void *stream)
+{
+    if (nsamples == 0)
+        return XSUM_OK;
+    if (out == nullptr || (uintptr_t)out % 8 != 0)
+        return xsum::api_fail(XSUM_EINVAL, "out is NULL or not 8-byte aligned");
+    if (nsamples > kClockMaxSamples || interval_ticks == 0 ||
+        (uint64_t)nsamples * interval_ticks > kClockMaxTicks)
+        return xsum::api_fail(XSUM_ERANGE, "clock probe: nsamples <= 2^20, interval >= 1 tick, "
+                                           "nsamples * interval <= 10 s");
+    hipLaunchKernelGGL(clock_probe_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, out,
+                       nsamples, interval_ticks);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? XSUM_OK : xsum::api_hip_fail(e, "kernel launch");
 }

@@ -283,3 +283,25 @@ int main(void) {
     T = xs.TruncRoot
     assert got == [ctypes.sizeof(T), T.value.offset, T.count.offset, T.bound_value.offset,
                    T.certified.offset, T.bits.offset, T.r.offset]
+
+
+def test_measurement_probes_reject_bad_arguments_on_the_host(lib):
+    lib.xsum_probe_clock.restype = ctypes.c_int
+    lib.xsum_probe_clock.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_void_p]
+    assert lib.xsum_probe_clock(None, 0, 1, None) == 0          # nothing to sample
+    assert lib.xsum_probe_clock(None, 4, 100, None) == 1
+    assert lib.xsum_probe_clock(4100, 4, 100, None) == 1        # not 8-byte aligned
+    assert lib.xsum_probe_clock(4096, (1 << 20) + 1, 1, None) == 5
+    assert lib.xsum_probe_clock(4096, 4, 0, None) == 5
+    assert lib.xsum_probe_clock(4096, 200_000, 5001, None) == 5   # over 10 s
+    assert "10 s" in _err(lib)
+    lib.xsum_probe_read.restype = ctypes.c_int
+    lib.xsum_probe_read.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+    assert lib.xsum_probe_read(4096, 0, None, None) == 0
+    assert lib.xsum_probe_read(4096, 24, 8192, None) == 1        # not a multiple of 16
+    lib.xsum_probe_flush.restype = ctypes.c_int
+    lib.xsum_probe_flush.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                     ctypes.c_void_p]
+    assert lib.xsum_probe_flush(4098, 8, 0, None) == 1
