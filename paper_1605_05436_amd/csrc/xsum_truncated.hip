@@ -19,10 +19,9 @@
 //                in order (the lane's share is a path of the summation tree).
 //                For r = 2 and 4 the list lives in registers (one compare
 //                and select per entry and digit); for r = 16 the same list
-//                lives in an LDS column with one row per digit index plus a
-//                mask of the active rows, so a digit costs one LDS add
-//                whatever r is (at one wave per SIMD, since the column takes
-//                a quarter of the LDS per wave)
+//                lives in r LDS slots in index order plus a mask of the
+//                active indices, so a digit costs one popcount and one LDS
+//                add whatever r is
 //   2. tree      lists are merged pairwise up the wave (shuffles), then the
 //                block (LDS), then the grid: each block publishes its list in
 //                the workspace and the last block to take a ticket merges
@@ -394,18 +393,18 @@ struct RegWalk : TWalk<R> {
     }
 };
 
-// A lane's list kept as a column of radix-2^32 rows in LDS (row i at
-// col[i * kTThreads]) plus a mask of the active rows: the same list, with
-// the entries' values at their index's row, so a digit whose index is active
-// is one LDS add at its row whatever r is.  Inactive rows are zero.
-constexpr int kRows = 66;
-
+// A lane's list kept in LDS as R slots in decreasing index order (slot j at
+// col[j * kTThreads]) plus a mask of the active indices in registers: the
+// slot of an active index is the number of active indices above it, so a
+// digit whose index is active costs one popcount and one LDS add whatever r
+// is, and the list takes R * 8 bytes per lane (several waves per SIMD).
+// Slots at or past the entry count hold stale values and are never read.
 template <int R>
-struct ColWalk {
+struct SlotWalk {
     uint64_t *col;
-    uint64_t act;     // active rows 0..63
-    uint32_t acth;    // active rows 64, 65
-    int cnt, lo;      // active rows; the lowest one when cnt == R
+    uint64_t act;     // active indices 0..63
+    uint32_t acth;    // active indices 64, 65
+    int cnt, lo;      // active indices; the lowest one when cnt == R
     int bidx;
     uint64_t bval;
     uint32_t drops, spec;
@@ -421,9 +420,6 @@ struct ColWalk {
         bval = 0;
         drops = 0;
         spec = 0;
-#pragma unroll
-        for (int i = 0; i < kRows; ++i)
-            lds_store(col + i * kTThreads, 0ull);
     }
     __device__ __forceinline__ void set_bit(int i)
     {
@@ -447,6 +443,15 @@ struct ColWalk {
     {
         return acth ? 95 - __builtin_clz(acth) : (act ? 63 - __builtin_clzll(act) : kNoIdx);
     }
+    // number of active indices above i (0 <= i <= 65)
+    __device__ __forceinline__ int above(int i) const
+    {
+        const int s = i + 1;
+        const uint32_t h = s >= 64 ? acth >> (s - 64) : acth;
+        const uint64_t l = s < 64 ? act >> s : 0ull;
+        return __builtin_popcount(h) + __builtin_popcountll(l);
+    }
+    __device__ __forceinline__ uint64_t *slot(int j) const { return col + j * kTThreads; }
     __device__ __forceinline__ void flush()
     {
         if (drops) {
@@ -454,7 +459,7 @@ struct ColWalk {
             drops = 0;
         }
     }
-    // (i, v) for an inactive row i (which holds zero)
+    // (i, v) for an inactive index i
     __device__ __forceinline__ void insert(int i, int64_t v)
     {
         if (cnt == R && i < lo) {
@@ -462,14 +467,18 @@ struct ColWalk {
             return;
         }
         if (cnt == R) {
-            uint64_t *pl = col + lo * kTThreads;
-            const int64_t ev = (int64_t)lds_load(pl);
-            lds_store(pl, 0ull);
+            // the lowest entry is the last slot
+            const int64_t ev = (int64_t)lds_load(slot(R - 1));
             clear_bit(lo);
             --cnt;
             bound_add(bidx, bval, lo, mag64(ev));
         }
-        lds_store(col + i * kTThreads, (uint64_t)v);
+        // the entries below i move down one slot
+        const int p = above(i);
+#pragma unroll 1
+        for (int j = cnt - 1; j >= p; --j)
+            lds_store(slot(j + 1), lds_load(slot(j)));
+        lds_store(slot(p), (uint64_t)v);
         set_bit(i);
         ++cnt;
         if (cnt == R)
@@ -478,8 +487,8 @@ struct ColWalk {
     template <int ND>
     __device__ __forceinline__ void add_leaf(int k, uint32_t d0, uint32_t d1, uint32_t d2, bool neg)
     {
-        // rows k..k+2 (k <= 63): the low word shifted down, rows 64 and 65
-        // from the high word shifted into place
+        // indices k..k+2 (k <= 63): the low word shifted down, indices 64
+        // and 65 from the high word shifted into place
         const uint32_t on = ((uint32_t)(act >> k) |
                              (k >= 62 ? acth << (64 - k) : 0u)) & 7u;
         const uint32_t nz = (d0 != 0 ? 1u : 0u) | (d1 != 0 ? 2u : 0u) |
@@ -488,14 +497,18 @@ struct ColWalk {
         const int64_t s0 = ((int64_t)d0 ^ sm) - sm;
         const int64_t s1 = ((int64_t)d1 ^ sm) - sm;
         const int64_t s2 = ND == 3 ? ((int64_t)d2 ^ sm) - sm : 0;
-        uint64_t *p = col + k * kTThreads;
         const uint32_t hit = nz & on;
+        // slots of k+2, k+1, k: each index's slot is one past the one above
+        // it when that one is active
+        const int a2 = above(k + 2);
+        const int a1 = a2 + (int)((on >> 2) & 1u);
+        const int a0 = a1 + (int)((on >> 1) & 1u);
         if (hit & 1u)
-            lds_add(p, (uint64_t)s0);
+            lds_add(slot(a0), (uint64_t)s0);
         if (hit & 2u)
-            lds_add(p + kTThreads, (uint64_t)s1);
+            lds_add(slot(a1), (uint64_t)s1);
         if (ND == 3 && (hit & 4u))
-            lds_add(p + 2 * kTThreads, (uint64_t)s2);
+            lds_add(slot(a2), (uint64_t)s2);
         const uint32_t miss = nz & ~on;
         const int top = k + 31 - __builtin_clz(miss | 1u);
         const bool drop = cnt == R && top < lo;
@@ -515,10 +528,8 @@ struct ColWalk {
         for (int j = 0; j < R; ++j) {
             const int h = highest();
             if (h != kNoIdx) {
-                uint64_t *ph = col + h * kTThreads;
                 out.idx[j] = h;
-                out.val[j] = (int64_t)lds_load(ph);
-                lds_store(ph, 0ull);
+                out.val[j] = (int64_t)lds_load(slot(j));
                 clear_bit(h);
             } else {
                 out.idx[j] = kNoIdx;
@@ -783,8 +794,8 @@ __global__ __launch_bounds__(kTThreads) void truncated_kernel(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0)
         blk_spec = 0;
-    __shared__ uint64_t cols[COL ? kRows : 1][kTThreads];
-    std::conditional_t<COL, ColWalk<R>, RegWalk<R>> W;
+    __shared__ uint64_t cols[COL ? R : 1][kTThreads];
+    std::conditional_t<COL, SlotWalk<R>, RegWalk<R>> W;
     if constexpr (COL)
         W.init(&cols[0][tid]);
     else
@@ -888,8 +899,9 @@ template <int FMT, int R>
 hipError_t launch_round_fmt(const void *x, uint64_t n, TCtl *ctl, TNode *nodes,
                             xsum_trunc_root_t *rec, int out_fmt, int cus, hipStream_t s)
 {
-    // r = 16: the LDS column (one add per digit whatever r is); r = 2 and
-    // 4: the register list (more waves per SIMD, fewer entries to compare)
+    // r = 16: the LDS slots (one add per digit whatever r is); r = 2 and
+    // 4: the register list (fewer entries to compare).  Either way four
+    // 256-thread blocks fit a compute unit (registers; LDS for the slots)
     constexpr bool COL = R > 4;
     constexpr int U = 8;
     using G = Geo<FMT>;
@@ -902,7 +914,7 @@ hipError_t launch_round_fmt(const void *x, uint64_t n, TCtl *ctl, TNode *nodes,
     const uint32_t tail = (uint32_t)((body % 16) / G::kBytes);
     const uint64_t per_block = (uint64_t)kTThreads * U;
     uint64_t blocks = (nvec + per_block - 1) / per_block;
-    const uint64_t cap = (uint64_t)cus * (COL ? 1 : 4);
+    const uint64_t cap = (uint64_t)cus * 4;
     if (blocks > cap)
         blocks = cap;
     if (blocks > (uint64_t)kMaxTBlocks)
