@@ -900,8 +900,7 @@ hipError_t launch_round_fmt(const void *x, uint64_t n, TCtl *ctl, TNode *nodes,
                             xsum_trunc_root_t *rec, int out_fmt, int cus, hipStream_t s)
 {
     // r = 16: the LDS slots (one add per digit whatever r is); r = 2 and
-    // 4: the register list (fewer entries to compare).  Either way four
-    // 256-thread blocks fit a compute unit (registers; LDS for the slots)
+    // 4: the register list (fewer entries to compare)
     constexpr bool COL = R > 4;
     constexpr int U = 8;
     using G = Geo<FMT>;
@@ -914,7 +913,16 @@ hipError_t launch_round_fmt(const void *x, uint64_t n, TCtl *ctl, TNode *nodes,
     const uint32_t tail = (uint32_t)((body % 16) / G::kBytes);
     const uint64_t per_block = (uint64_t)kTThreads * U;
     uint64_t blocks = (nvec + per_block - 1) / per_block;
-    const uint64_t cap = (uint64_t)cus * 4;
+    // one resident wave of blocks: as many per compute unit as registers
+    // and LDS allow (a block past that would run alone at the end)
+    static const int per_cu = [] {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, truncated_kernel<FMT, R, U, COL>, kTThreads, 0) != hipSuccess || nb < 1)
+            nb = 1;
+        return nb;
+    }();
+    const uint64_t cap = (uint64_t)cus * (uint64_t)per_cu;
     if (blocks > cap)
         blocks = cap;
     if (blocks > (uint64_t)kMaxTBlocks)
