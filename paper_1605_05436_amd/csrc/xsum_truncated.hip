@@ -258,6 +258,7 @@ struct TWalk {
     uint32_t negs;
     uint32_t drops;
     uint32_t spec;
+    uint32_t emax;
 };
 
 template <int R>
@@ -270,6 +271,7 @@ __device__ __forceinline__ void tw_init(TWalk<R> &W)
     W.negs = 0;
     W.drops = 0;
     W.spec = 0;
+    W.emax = 0;
 }
 
 template <int R>
@@ -399,6 +401,16 @@ struct RegWalk : TWalk<R> {
 // digit whose index is active costs one popcount and one LDS add whatever r
 // is, and the list takes R * 8 bytes per lane (several waves per SIMD).
 // Slots at or past the entry count hold stale values and are never read.
+// +d or -d (m = 0 or all ones) as a 64-bit two's complement value: the low
+// word (d ^ m) - m, the high word m - m minus the borrow.
+__device__ __forceinline__ int64_t signed_digit(uint32_t d, uint32_t m)
+{
+    uint32_t b;
+    const uint32_t lo = __builtin_subc(d ^ m, m, 0u, &b);
+    const uint32_t hi = __builtin_subc(m, m, b, &b);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 template <int R>
 struct SlotWalk {
     uint64_t *col;
@@ -407,7 +419,7 @@ struct SlotWalk {
     int cnt, lo;      // active indices; the lowest one when cnt == R
     int bidx;
     uint64_t bval;
-    uint32_t drops, spec;
+    uint32_t drops, spec, emax;
 
     __device__ __forceinline__ void init(uint64_t *c)
     {
@@ -420,6 +432,7 @@ struct SlotWalk {
         bval = 0;
         drops = 0;
         spec = 0;
+        emax = 0;
     }
     __device__ __forceinline__ void set_bit(int i)
     {
@@ -493,10 +506,10 @@ struct SlotWalk {
                              (k >= 62 ? acth << (64 - k) : 0u)) & 7u;
         const uint32_t nz = (d0 != 0 ? 1u : 0u) | (d1 != 0 ? 2u : 0u) |
                             (ND == 3 && d2 != 0 ? 4u : 0u);
-        const int64_t sm = neg ? -1 : 0;
-        const int64_t s0 = ((int64_t)d0 ^ sm) - sm;
-        const int64_t s1 = ((int64_t)d1 ^ sm) - sm;
-        const int64_t s2 = ND == 3 ? ((int64_t)d2 ^ sm) - sm : 0;
+        const uint32_t sm = neg ? ~0u : 0u;
+        const int64_t s0 = signed_digit(d0, sm);
+        const int64_t s1 = signed_digit(d1, sm);
+        const int64_t s2 = ND == 3 ? signed_digit(d2, sm) : 0;
         const uint32_t hit = nz & on;
         // slots of k+2, k+1, k: each index's slot is one past the one above
         // it when that one is active
@@ -543,15 +556,15 @@ struct SlotWalk {
 
 // Element decoders: exponent position q of the significand's bit 0 in units
 // of 2^-1074, split at the radix-2^32 digit boundary.  Infinities and NaNs
-// set `spec` and add nothing.
+// add nothing; the walk keeps the largest exponent field it met (emax), and
+// the tile loop records the special values of a tile where it is all ones.
 template <typename WT>
 __device__ __forceinline__ void leaf_f64(WT &W, uint32_t lo, uint32_t hi)
 {
     const uint32_t e = (hi >> 20) & 0x7ffu;
+    W.emax = max(W.emax, e);
     const bool neg = (hi >> 31) != 0;
     const bool special = e == 0x7ffu;
-    if (special)
-        W.spec |= special_bits(((hi & 0xfffffu) | lo) != 0, neg);
     const uint32_t mh = special ? 0u : ((hi & 0xfffffu) | (e ? 0x100000u : 0u));
     const uint64_t m = ((uint64_t)mh << 32) | (special ? 0u : lo);
     const int q = e ? (int)e - 1 : 0;
@@ -565,14 +578,9 @@ template <typename WT>
 __device__ __forceinline__ void leaf_f32(WT &W, uint32_t b)
 {
     const uint32_t e = (b >> 23) & 0xffu;
+    W.emax = max(W.emax, e);
     const bool neg = (b >> 31) != 0;
-    uint32_t m = b & 0x7fffffu;
-    if (e == 0xffu) {
-        W.spec |= special_bits(m != 0, neg);
-        m = 0;
-    } else if (e) {
-        m |= 1u << 23;
-    }
+    const uint32_t m = e == 0xffu ? 0u : ((b & 0x7fffffu) | (e ? 1u << 23 : 0u));
     const int q = (e ? (int)e - 1 : 0) + 925;
     const uint64_t w = (uint64_t)m << (q & 31);
     W.template add_leaf<2>(q >> 5, (uint32_t)w, (uint32_t)(w >> 32), 0u, neg);
@@ -582,18 +590,53 @@ template <typename WT>
 __device__ __forceinline__ void leaf_bf16(WT &W, uint32_t h)
 {
     const uint32_t e = (h >> 7) & 0xffu;
+    W.emax = max(W.emax, e);
     const bool neg = ((h >> 15) & 1u) != 0;
-    uint32_t m = h & 0x7fu;
-    if (e == 0xffu) {
-        W.spec |= special_bits(m != 0, neg);
-        m = 0;
-    } else if (e) {
-        m |= 1u << 7;
-    }
+    const uint32_t m = e == 0xffu ? 0u : ((h & 0x7fu) | (e ? 1u << 7 : 0u));
     const int q = (e ? (int)e - 1 : 0) + 941;
     const uint64_t w = (uint64_t)m << (q & 31);
     W.template add_leaf<2>(q >> 5, (uint32_t)w, (uint32_t)(w >> 32), 0u, neg);
 }
+
+// Special-value bits of one element (0 for a finite one).
+__device__ __forceinline__ uint32_t spec_f64(uint32_t lo, uint32_t hi)
+{
+    return ((hi >> 20) & 0x7ffu) == 0x7ffu
+               ? special_bits(((hi & 0xfffffu) | lo) != 0, (hi >> 31) != 0)
+               : 0u;
+}
+
+__device__ __forceinline__ uint32_t spec_f32(uint32_t b)
+{
+    return ((b >> 23) & 0xffu) == 0xffu ? special_bits((b & 0x7fffffu) != 0, (b >> 31) != 0)
+                                        : 0u;
+}
+
+__device__ __forceinline__ uint32_t spec_bf16(uint32_t h)
+{
+    return ((h >> 7) & 0xffu) == 0xffu ? special_bits((h & 0x7fu) != 0, ((h >> 15) & 1u) != 0)
+                                       : 0u;
+}
+
+template <int FMT>
+__device__ __forceinline__ uint32_t spec_vector(const vec4u &q)
+{
+    if constexpr (FMT == XSUM_F64) {
+        return spec_f64(q.x, q.y) | spec_f64(q.z, q.w);
+    } else if constexpr (FMT == XSUM_F32) {
+        return spec_f32(q.x) | spec_f32(q.y) | spec_f32(q.z) | spec_f32(q.w);
+    } else {
+        uint32_t r = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            r |= spec_bf16(q[c] & 0xffffu) | spec_bf16(q[c] >> 16);
+        return r;
+    }
+}
+
+// the exponent field of an infinity or NaN
+template <int FMT>
+constexpr uint32_t kAllOnes = FMT == XSUM_F64 ? 0x7ffu : 0xffu;
 
 template <int FMT, typename WT>
 __device__ __forceinline__ void add_vector(WT &W, const vec4u &q)
@@ -621,10 +664,15 @@ __device__ __forceinline__ void add_one(WT &W, const uint8_t *p)
     if constexpr (FMT == XSUM_F64) {
         const uint32_t *w = (const uint32_t *)p;
         leaf_f64(W, w[0], w[1]);
+        W.spec |= spec_f64(w[0], w[1]);
     } else if constexpr (FMT == XSUM_F32) {
-        leaf_f32(W, *(const uint32_t *)p);
+        const uint32_t b = *(const uint32_t *)p;
+        leaf_f32(W, b);
+        W.spec |= spec_f32(b);
     } else {
-        leaf_bf16(W, *(const uint16_t *)p);
+        const uint32_t h = *(const uint16_t *)p;
+        leaf_bf16(W, h);
+        W.spec |= spec_bf16(h);
     }
 }
 
@@ -804,18 +852,36 @@ __global__ __launch_bounds__(kTThreads) void truncated_kernel(
     // 1. leaves: vectors tid + j*T of each tile of U*T (T threads in the grid)
     const vec4u *v = (const vec4u *)(x + (uint64_t)head * G::kBytes);
     const uint64_t T = (uint64_t)gridDim.x * kTThreads;
-    for (uint64_t base = (uint64_t)blockIdx.x * kTThreads + tid; base < nvec; base += U * T) {
+    for (uint64_t tb = (uint64_t)blockIdx.x * kTThreads; tb < nvec; tb += U * T) {
+        const uint64_t base = tb + tid;
         vec4u q[U];
+        if (tb + (kTThreads - 1) + (uint64_t)(U - 1) * T < nvec) {
+            // the whole block's tile is in range
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const uint64_t i = base + (uint64_t)j * T;
-            q[j] = vec4u{0u, 0u, 0u, 0u};
-            if (i < nvec)
-                q[j] = __builtin_nontemporal_load(v + i);
+            for (int j = 0; j < U; ++j)
+                q[j] = __builtin_nontemporal_load(v + base + (uint64_t)j * T);
+        } else {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const uint64_t i = base + (uint64_t)j * T;
+                q[j] = vec4u{0u, 0u, 0u, 0u};
+                if (i < nvec)
+                    q[j] = __builtin_nontemporal_load(v + i);
+            }
         }
 #pragma clang loop unroll(full)
         for (int j = 0; j < U; ++j)
             add_vector<FMT>(W, q[j]);
+        if (__builtin_expect(W.emax == kAllOnes<FMT>, 0)) {
+            // rare: read the tile again rather than keep it in registers
+#pragma unroll 1
+            for (int j = 0; j < U; ++j) {
+                const uint64_t i = base + (uint64_t)j * T;
+                if (i < nvec)
+                    W.spec |= spec_vector<FMT>(v[i]);
+            }
+        }
+        W.emax = 0;
     }
     if (blockIdx.x == 0) {
         if ((uint32_t)tid < head)

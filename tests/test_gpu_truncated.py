@@ -186,3 +186,28 @@ def test_pass_records_do_not_depend_on_scheduling(ws):
         a = bytes(run_pass(t, len(bits), "f64", r, ws))
         for _ in range(3):
             assert bytes(run_pass(t, len(bits), "f64", r, ws)) == a
+
+
+@pytest.mark.parametrize("fmt", NAMES)
+def test_special_values_inside_tiles(fmt, ws):
+    """Infinities and NaNs met in the middle of a lane's tiles (not only in
+    the head or tail): every pass records them and certifies the special
+    result."""
+    n = 200_003
+    bits = workloads.family("mixed", n, 60, seed=9, fmt=fmt) if fmt != "f64" \
+        else workloads.config1(n, seed=9)
+    rng = np.random.default_rng(3)
+    allones = {"f64": (0x7FF0000000000000, 0xFFF0000000000000, 0x7FF8000000000001),
+               "f32": (0x7F800000, 0xFF800000, 0x7FC00001),
+               "bf16": (0x7F80, 0xFF80, 0x7FC1)}[fmt]
+    for case in ((0,), (1,), (0, 1), (2,), (0, 0)):
+        b = bits.copy()
+        at = rng.choice(np.arange(64, n - 64), size=len(case), replace=False)
+        for pos, which in zip(at, case):
+            b[pos] = allones[which]
+        want = tuple(oracle.oracle_sum(b, fmt))
+        t = to_device(b)
+        assert run_blocking(t, n, fmt, ws)[:2] == want, case
+        for r in (2, 4, 16):
+            rec = run_pass(t, n, fmt, r, ws)
+            assert rec.special and rec.certified and (rec.bits, rec.flags) == want, (case, r)
