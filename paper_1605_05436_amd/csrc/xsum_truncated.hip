@@ -395,12 +395,6 @@ struct RegWalk : TWalk<R> {
     }
 };
 
-// A lane's list kept in LDS as R slots in decreasing index order (slot j at
-// col[j * kTThreads]) plus a mask of the active indices in registers: the
-// slot of an active index is the number of active indices above it, so a
-// digit whose index is active costs one popcount and one LDS add whatever r
-// is, and the list takes R * 8 bytes per lane (several waves per SIMD).
-// Slots at or past the entry count hold stale values and are never read.
 // +d or -d (m = 0 or all ones) as a 64-bit two's complement value: the low
 // word (d ^ m) - m, the high word m - m minus the borrow.
 __device__ __forceinline__ int64_t signed_digit(uint32_t d, uint32_t m)
@@ -411,6 +405,12 @@ __device__ __forceinline__ int64_t signed_digit(uint32_t d, uint32_t m)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// A lane's list kept in LDS as R slots in decreasing index order (slot j at
+// col[j * kTThreads]) plus a mask of the active indices in registers: the
+// slot of an active index is the number of active indices above it, so a
+// digit whose index is active costs one popcount and one LDS add whatever r
+// is, and the list takes R * 8 bytes per lane (several waves per SIMD).
+// Slots at or past the entry count hold stale values and are never read.
 template <int R>
 struct SlotWalk {
     uint64_t *col;
@@ -464,6 +464,12 @@ struct SlotWalk {
         const uint64_t l = s < 64 ? act >> s : 0ull;
         return __builtin_popcount(h) + __builtin_popcountll(l);
     }
+    // the mask from index k up (k <= 63): bit b is index k + b, the two
+    // indices above 63 shifted in below the top
+    __device__ __forceinline__ uint64_t window(int k) const
+    {
+        return (act >> k) | (((uint64_t)acth << 1) << (63 - k));
+    }
     __device__ __forceinline__ uint64_t *slot(int j) const { return col + j * kTThreads; }
     __device__ __forceinline__ void flush()
     {
@@ -502,8 +508,8 @@ struct SlotWalk {
     {
         // indices k..k+2 (k <= 63): the low word shifted down, indices 64
         // and 65 from the high word shifted into place
-        const uint32_t on = ((uint32_t)(act >> k) |
-                             (k >= 62 ? acth << (64 - k) : 0u)) & 7u;
+        const uint64_t wdw = window(k);
+        const uint32_t on = (uint32_t)wdw & 7u;
         const uint32_t nz = (d0 != 0 ? 1u : 0u) | (d1 != 0 ? 2u : 0u) |
                             (ND == 3 && d2 != 0 ? 4u : 0u);
         const uint32_t sm = neg ? ~0u : 0u;
@@ -511,9 +517,11 @@ struct SlotWalk {
         const int64_t s1 = signed_digit(d1, sm);
         const int64_t s2 = ND == 3 ? signed_digit(d2, sm) : 0;
         const uint32_t hit = nz & on;
-        // slots of k+2, k+1, k: each index's slot is one past the one above
-        // it when that one is active
-        const int a2 = above(k + 2);
+        // slots of k+2, k+1, k: the active indices above k+2 are the window's
+        // bits from 3 up and, for k < 2, the indices above 63 past its top;
+        // each index's slot is one past the one above it when that is active
+        const int a2 = __builtin_popcountll(wdw >> 3) +
+                       __builtin_popcount((uint32_t)((uint64_t)acth >> k));
         const int a1 = a2 + (int)((on >> 2) & 1u);
         const int a0 = a1 + (int)((on >> 1) & 1u);
         if (hit & 1u)
