@@ -416,7 +416,8 @@ struct SlotWalk {
     uint64_t *col;
     uint64_t act;     // active indices 0..63
     uint32_t acth;    // active indices 64, 65
-    int cnt, lo;      // active indices; the lowest one when cnt == R
+    int cnt;          // active indices
+    int lo;           // the lowest active index when cnt == R, else kNoIdx
     int bidx;
     uint64_t bval;
     uint32_t drops, spec, emax;
@@ -481,7 +482,7 @@ struct SlotWalk {
     // (i, v) for an inactive index i
     __device__ __forceinline__ void insert(int i, int64_t v)
     {
-        if (cnt == R && i < lo) {
+        if (i < lo) {
             bound_add(bidx, bval, i, mag64(v));
             return;
         }
@@ -491,6 +492,7 @@ struct SlotWalk {
             clear_bit(lo);
             --cnt;
             bound_add(bidx, bval, lo, mag64(ev));
+            lo = kNoIdx;
         }
         // the entries below i move down one slot
         const int p = above(i);
@@ -506,8 +508,7 @@ struct SlotWalk {
     template <int ND>
     __device__ __forceinline__ void add_leaf(int k, uint32_t d0, uint32_t d1, uint32_t d2, bool neg)
     {
-        // indices k..k+2 (k <= 63): the low word shifted down, indices 64
-        // and 65 from the high word shifted into place
+        // which of the indices k..k+2 (k <= 63) are active
         const uint64_t wdw = window(k);
         const uint32_t on = (uint32_t)wdw & 7u;
         const uint32_t nz = (d0 != 0 ? 1u : 0u) | (d1 != 0 ? 2u : 0u) |
@@ -532,7 +533,7 @@ struct SlotWalk {
             lds_add(slot(a2), (uint64_t)s2);
         const uint32_t miss = nz & ~on;
         const int top = k + 31 - __builtin_clz(miss | 1u);
-        const bool drop = cnt == R && top < lo;
+        const bool drop = top < lo;     // below a full list
         drops += (miss && drop) ? 1u : 0u;
         if (miss && !drop) {
             flush();
