@@ -989,7 +989,9 @@ hipError_t launch_round_fmt(const void *x, uint64_t n, TCtl *ctl, TNode *nodes,
     const uint64_t per_block = (uint64_t)kTThreads * U;
     uint64_t blocks = (nvec + per_block - 1) / per_block;
     // one resident wave of blocks: as many per compute unit as registers
-    // and LDS allow (a block past that would run alone at the end)
+    // and LDS allow (a block past that would run alone at the end); asked
+    // once per instance, on the first call's device (the answer depends only
+    // on the kernel and the architecture)
     static const int per_cu = [] {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
