@@ -117,6 +117,35 @@ def cpu_baseline_full(bits, fmt, terms=None, budget_s=3.0):
     return want, closed, threads, times[len(times) // 2], len(times), cond
 
 
+def cpu_single_thread_refs(bits, want_bits, n_int, n_fsum):
+    """Single-threaded CPU references on leading samples of a binary64
+    input: the oracle's plain Python-int sum (n_int elements) and math.fsum
+    (n_fsum elements, a correctly rounded library sum that the oracle's
+    rounding must equal).  Returns a dict of rates; when the samples are the
+    whole input, also whether fsum's result equals the oracle's bits."""
+    import math
+    import oracle
+    m = min(len(bits), n_int)
+    t0 = time.time()
+    got_int = tuple(oracle.oracle_sum(bits[:m], "f64"))
+    t_int = time.time() - t0
+    f = min(len(bits), n_fsum)
+    vals = bits[:f].view(np.float64).tolist()
+    t0 = time.time()
+    fs = math.fsum(vals)
+    t_fs = time.time() - t0
+    fs_bits = struct.unpack("<Q", struct.pack("<d", fs))[0]
+    out = {"python_int": {"gelem_s": round(m / t_int / 1e9, 5), "elements": m,
+                          "seconds": round(t_int, 3)},
+           "math_fsum": {"gelem_s": round(f / t_fs / 1e9, 5), "elements": f,
+                         "seconds": round(t_fs, 3)}}
+    if m == len(bits):
+        out["python_int"]["same_bits_as_binned"] = got_int[0] == want_bits
+    if f == len(bits):
+        out["math_fsum"]["same_bits_as_oracle"] = fs_bits == want_bits
+    return out
+
+
 def cpu_baseline_sample(pieces, threads=16):
     """The cpu_baseline leg for many sums: the oracle on a bounded sample of
     (bit-pattern array, format) pieces, timed.  Returns (results, elements,
@@ -478,6 +507,11 @@ def bench_single(args):
                                "value_1core": round(m1 / one_s / 1e9, 4),
                                "sample_1core": "the first %d elements on 1 thread, "
                                                "accumulation only" % m1}
+        if args.workload == "single" and fmt == "f64":
+            # the oracle's plain Python-int sum and math.fsum, single-threaded,
+            # on leading samples (the whole input would take minutes)
+            rec["cpu_baseline"]["single_thread"] = cpu_single_thread_refs(
+                bits, want_bits, 1 << 20, 1 << 24)
     print(json.dumps(rec), flush=True)
 
 
@@ -667,6 +701,9 @@ def bench_config1(args):
            "cpu_baseline": {"value": round(n / cpu_s / 1e9, 4), "unit": "Gelem/s",
                             "cores": threads, "kind": "oracle",
                             "sample": "the full 10^6 input, median of %d runs" % cpu_runs}}
+    if not args.no_cpu_baseline:
+        # single-threaded references over the whole input
+        rec["cpu_baseline"]["single_thread"] = cpu_single_thread_refs(bits, want[0], n, n)
     print(json.dumps(rec), flush=True)
 
 
