@@ -44,7 +44,11 @@ def test_clock_samples_advance_at_the_requested_interval():
     torch.cuda.synchronize()
     s = out.cpu().numpy().reshape(-1, 2)
     rt, ck = np.diff(s[:, 0]), np.diff(s[:, 1])
-    assert (rt > interval // 2).all() and (rt < 4 * interval).all()
+    # the constant-rate counter advances by about the interval (a sample can
+    # be taken a little late), the shader-clock counter never goes back
+    assert (rt > interval // 2).all() and np.median(rt) < 2 * interval
+    assert (ck > 0).all()
     mhz = ck / rt * 100.0
-    # a shader clock between 100 MHz and the 2.4 GHz peak, with margin
-    assert (mhz > 100).all() and (mhz < 3000).all(), mhz
+    # a plausible shader clock: below the 2.4 GHz peak with margin, and
+    # well above the 100 MHz reference while a wave is running
+    assert 200 < np.median(mhz) < 3000, mhz
