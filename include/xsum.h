@@ -275,7 +275,8 @@ size_t xsum_truncated_workspace_size(void);
  *              bytes, zero-filled before its first use; every pass leaves
  *              it as it found it.  Calls sharing a workspace must be ordered.
  * The record does not depend on scheduling: the tree's shape is fixed by n,
- * the input's address and the device's compute-unit count.
+ * the input's address, the device's compute-unit count and how many blocks
+ * of the pass's kernel fit one compute unit (a property of the build).
  */
 xsum_status_t xsum_truncated_round(const void *x, uint64_t n, int dtype, int out_dtype,
                                    int r, xsum_trunc_root_t *root_dev, void *workspace,
